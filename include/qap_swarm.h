@@ -1,0 +1,171 @@
+/*
+ * qap_swarm.h -- C ABI of the MI355X (gfx950) implementation of the
+ * multi-swarm discrete particle swarm optimisation for the Quadratic
+ * Assignment Problem of Szwed & Chmiel (arXiv:1504.05158).
+ *
+ * Problem (Sec. 2.1, eq. qap): n facilities, n locations, flow matrix F and
+ * distance matrix D (both n x n, row-major int32).  A solution is a
+ * permutation p with p[i] = location of facility i (0-based); its cost is
+ *     C(p) = sum_{i,j} F[i][j] * D[p[i]][p[j]]
+ * (diagonal terms included: the installation cost of Sec. 2.1).
+ *
+ * Method (Sec. 3.1-3.2): every particle holds a solution X (a permutation
+ * matrix, rows = locations, columns = facilities) and a real n x n velocity V.
+ * One iteration per particle:
+ *   X(t+1) = S_x(X(t) + V(t))                 S_x = SecondTarget (Alg. 1)
+ *   V(t+1) = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X))   (eq. velocity)
+ * then the goal of X(t+1), one best-improvement pair exchange (local
+ * improvement; optional), the particle best P^L, the swarm best P^G, and in
+ * migration mode Alg. 2 every `migration_period` iterations.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: QAP_OK (0) or a negative QAP_ERR_* code.  No C++
+ *    exception crosses the ABI.  A device error is sticky: once it has been
+ *    seen, every later call on the handle returns QAP_ERR_DEVICE.
+ *  - Host pointers only, caller-owned; the library copies what it needs.
+ *    Device memory is owned by the handle and freed by qap_swarm_destroy.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ *  - Random numbers come from a Philox4x32-10 counter-based stream keyed by
+ *    the seed, so a run is a deterministic function of (instance, params).
+ */
+#ifndef QAP_SWARM_H
+#define QAP_SWARM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QAP_OK = 0,
+    QAP_ERR_INVALID_ARG = -1, /* NULL pointer or a parameter outside its range */
+    QAP_ERR_RANGE = -2,       /* F, D values too wide for the requested / any exact path */
+    QAP_ERR_NOMEM = -3,       /* device or host allocation failed */
+    QAP_ERR_DEVICE = -4,      /* HIP runtime error (sticky) */
+    QAP_ERR_UNSUPPORTED = -5  /* valid request this build does not provide */
+};
+
+enum { QAP_SV_RAW = 0, QAP_SV_NORM = 1 };          /* S_v of Sec. 3.1 */
+enum { QAP_INDEPENDENT = 0, QAP_MIGRATION = 1 };   /* swarm modes (Sec. 3.2) */
+enum { QAP_PATH_AUTO = 0, QAP_PATH_INT8_MFMA = 1, QAP_PATH_INT32 = 2 }; /* swap-delta contraction */
+enum { QAP_ENGINE_FUSED = 0, QAP_ENGINE_PLAIN = 1 }; /* one fused kernel per step vs per-stage kernels */
+
+typedef struct qap_swarm qap_swarm; /* opaque handle */
+
+/* A QAP instance (Sec. 2.1): F and D are n x n row-major, 2 <= n <= 256. */
+typedef struct {
+    int32_t n;
+    const int32_t* F;
+    const int32_t* D;
+} qap_instance;
+
+/* Run parameters (the columns of Table 1 plus the readings this library fixes).
+ *  num_swarms m >= 1, particles_per_swarm S >= 1 (particle index g*S + s).
+ *  c1, c2, c3 in [0, 1]: inertia, self-recognition, social factor (Sec. 2.2).
+ *  vmax > 0: bound of S_v (Sec. 3.1).  velocity_kernel: QAP_SV_RAW / QAP_SV_NORM.
+ *  st_depth in [0, n-1]: SecondTarget depth d (Alg. 1, d < n).
+ *  mode, migration_factor, migration_period: Alg. 2 with depth
+ *    floor(migration_factor * m), which must be < m/2; the period is >= 1.
+ *  local_search: 1 = one best-improvement pair exchange per particle-iteration.
+ *  delta_path: contraction used for the pair-exchange deltas (AUTO picks int8
+ *    MFMA when every F, D entry is in [-128, 127]).
+ *  engine: QAP_ENGINE_FUSED (one kernel per step, replayed from a HIP graph) or
+ *    QAP_ENGINE_PLAIN (one kernel per stage, int32 contraction).
+ *  seed: key of the random stream.  stream: hipStream_t to run on (NULL = the
+ *    library's own stream). */
+typedef struct {
+    int32_t num_swarms;
+    int32_t particles_per_swarm;
+    float c1, c2, c3;
+    float vmax;
+    int32_t velocity_kernel;
+    int32_t st_depth;
+    int32_t mode;
+    float migration_factor;
+    int32_t migration_period;
+    int32_t local_search;
+    int32_t delta_path;
+    int32_t engine;
+    uint64_t seed;
+    void* stream;
+} qap_params;
+
+/* Host-side copy of one instance's state (checkpoint / inspection).  Every
+ * pointer is caller-owned and may be NULL to skip that member.  P = m*S.
+ *   V       float  [P][n][n]  row = location, column = facility
+ *   X, PL   int32  [P][n]     current solution and particle best (p[i] = location)
+ *   goal, goalPL  int64 [P]
+ *   PG      int32  [m][n],  goalPG int64 [m]   swarm bests
+ *   best_*  best solution ever seen, the iteration, swarm and member it came from
+ *   iteration: number of completed iterations (0 after init). */
+typedef struct {
+    float* V;
+    int32_t* X;
+    int32_t* PL;
+    int64_t* goal;
+    int64_t* goalPL;
+    int32_t* PG;
+    int64_t* goalPG;
+    int32_t* best_perm;
+    int64_t best_goal;
+    int32_t best_iter, best_swarm, best_particle;
+    int32_t iteration;
+} qap_state;
+
+/* Create a handle for one instance and run the initialisation (iteration 0:
+ * random permutations, random velocities passed through S_v, goals, bests).
+ * Errors: QAP_ERR_INVALID_ARG (NULL, n outside [2,256], a parameter outside
+ * the ranges above), QAP_ERR_RANGE (int8 path requested on wider data, or
+ * n * max|F| * max|D| >= 2^31 so no exact int32 contraction exists),
+ * QAP_ERR_NOMEM, QAP_ERR_DEVICE.  On error *out is NULL. */
+int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out);
+
+/* Same for `count` independent instances that step together (each with its
+ * own params and seed; the engine, delta_path and stream of prms[0] apply to
+ * all).  Instance k is addressed by index k in the calls below. */
+int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count,
+                         qap_swarm** out);
+
+/* Enqueue `iterations` >= 0 iterations on the handle's stream and return
+ * without waiting.  Device errors surface here or on a later call. */
+int qap_swarm_step(qap_swarm* h, int32_t iterations);
+
+/* Wait for the handle's stream. */
+int qap_swarm_sync(qap_swarm* h);
+
+/* Best solution ever seen by an instance (waits first).  perm: n entries,
+ * may be NULL; goal / iter_found may be NULL. */
+int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found);
+
+/* Current swarm-best goals (m entries) of an instance (waits first). */
+int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals);
+
+/* Copy an instance's state to / from host buffers (waits first).  set_state
+ * validates every permutation and returns QAP_ERR_INVALID_ARG on a bad one;
+ * it requires V, X, PL, goal, goalPL, PG, goalPG and best_perm. */
+int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st);
+int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st);
+
+/* Evaluate `count` permutations (host, [count][n]) of an instance with the
+ * handle's device contraction path: goals [count] and, if deltas is not NULL,
+ * the full pair-exchange delta matrices [count][n][n] (delta(a,b) =
+ * C(p with a, b exchanged) - C(p), zero diagonal).  Waits for the result. */
+int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count,
+                   int64_t* goals, int64_t* deltas);
+
+/* Path actually used by an instance: QAP_PATH_INT8_MFMA or QAP_PATH_INT32 in
+ * *delta_path, and 1 in *symmetric if F and D are both symmetric. */
+int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric);
+
+/* Release every device and host resource of the handle (NULL is a no-op). */
+void qap_swarm_destroy(qap_swarm* h);
+
+/* Static text for a return code. */
+const char* qap_swarm_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QAP_SWARM_H */

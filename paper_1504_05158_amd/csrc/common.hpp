@@ -1,0 +1,129 @@
+// Shared device-side definitions of the QAP swarm library (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qap {
+
+constexpr int kWave = 64;
+constexpr int kMaxN = 256;
+
+// Best-ever record of an instance (device memory).
+struct BestRec {
+    long long goal;
+    int iter, swarm, member;
+    int pad;
+    uint8_t perm[kMaxN];
+};
+
+// Per-swarm minimum of the current goals of one iteration.
+struct SwarmMin {
+    long long goal;
+    int member;
+    int pad;
+};
+
+// Everything a kernel needs to know about one instance.  Device pointers.
+// Particle k of the instance is member k % S of swarm k / S.
+struct InstDesc {
+    int n;          // problem size
+    int npad;       // n rounded up to a multiple of 32 (MFMA tiles)
+    int m, S, P;    // swarms, members per swarm, particles
+    float c1, c2, c3, vmax;
+    int norm;       // S_v: 0 raw, 1 column-normalised
+    int depth;      // SecondTarget depth
+    int ls;         // one pair exchange per iteration
+    int migrate, migr_d, period;
+    int sym;        // F and D both symmetric
+    int path;       // 1 int8 MFMA, 2 int32
+    uint64_t seed;
+    // instance data
+    const int* F32;         // [n][n]
+    const int* D32;         // [n][n]
+    const int8_t* F8;       // [npad][npad] zero padded (int8 path) : F
+    const int8_t* D8;       // [npad][npad] : D
+    const int8_t* FT8;      // [npad][npad] : F^T
+    const int8_t* DT8;      // [npad][npad] : D^T
+    // particle state; index [k] by particle, two buffers selected by iteration parity
+    float* V[2];            // [P][n][n] row = location, column = facility
+    uint8_t* X[2];          // [P][n]   p[i] = location of facility i
+    uint8_t* PL;            // [P][n]
+    long long* goal;        // [P]
+    long long* goalPL;      // [P]
+    uint8_t* PG;            // [m][n]
+    long long* goalPG;      // [m]
+    SwarmMin* smin;         // [m]
+    BestRec* best;          // [1]
+    int* iter;              // [1] completed iterations
+    uint8_t* Xnew;          // [P][n] SecondTarget output (per-stage engine)
+    int* scratch;           // per-block contraction scratch (per-stage engine)
+};
+
+// ---------------------------------------------------------------- wave ops
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK,
+                                                      0xF, false));
+}
+
+// Maximum over the 64 lanes, returned to every lane (uniform).
+__device__ __forceinline__ float wave_max(float v)
+{
+    v = fmaxf(v, dpp_f32<0xB1>(v));        // quad_perm [1,0,3,2]
+    v = fmaxf(v, dpp_f32<0x4E>(v));        // quad_perm [2,3,0,1]
+    v = fmaxf(v, dpp_f32<0x141>(v));       // row_half_mirror
+    v = fmaxf(v, dpp_f32<0x140>(v));       // row_mirror: every lane holds its row's max
+    v = fmaxf(v, dpp_f32<0x142, 0xA>(v));  // row_bcast15 into rows 1, 3
+    v = fmaxf(v, dpp_f32<0x143, 0xC>(v));  // row_bcast31 into rows 2, 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ int wave_sum_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+__device__ __forceinline__ int wave_incl_scan_i32(int v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off, kWave);
+        if (l >= off) v += u;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int readlane_i32(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ float readlane_f32(float v, int lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ uint64_t ballot64(bool p) { return (uint64_t)__ballot(p); }
+
+// Lexicographic (delta, a, b) minimum over the wave; result uniform.
+__device__ __forceinline__ void wave_argmin_pair(long long& d, int& a, int& b)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const long long d2 = __shfl_xor(d, off, kWave);
+        const int a2 = __shfl_xor(a, off, kWave);
+        const int b2 = __shfl_xor(b, off, kWave);
+        const bool take = (d2 < d) || (d2 == d && (a2 < a || (a2 == a && b2 < b)));
+        if (take) { d = d2; a = a2; b = b2; }
+    }
+}
+
+}  // namespace qap

@@ -1,0 +1,30 @@
+// Launch interface between the host runtime and the kernels.
+#pragma once
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace qap {
+
+// Initialisation (iteration 0) of one instance.
+hipError_t launch_init(const InstDesc& d, hipStream_t st);
+
+// Per-stage engine: one iteration of one instance (S_x, velocity,
+// goal + deltas + local search, swarm bests, finish).
+hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st);
+
+// Goal (+ deltas) of `count` permutations [count][n] (device) on the int32 path.
+// mode 1: eval into goals/deltas; mode 2: initial goals of the particles.
+hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, const uint8_t* perms, int count,
+                                 int mode, long long* goals, long long* deltas, hipStream_t st);
+
+// Swarm bests + finish (best-ever, migration, iteration counter).
+hipError_t launch_bests(const InstDesc& d, int init, int* order, hipStream_t st);
+
+// Fused engine: one iteration of one instance in one kernel, plus bests.
+hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st);
+
+// Goal (+ deltas) of `count` permutations on the int8 MFMA path (eval only).
+hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
+                            long long* deltas, hipStream_t st);
+
+}  // namespace qap

@@ -1,0 +1,494 @@
+// Host runtime behind the C ABI of include/qap_swarm.h: parameter checks,
+// range checks and path choice, device buffers, the per-iteration launch
+// sequence (or its HIP graph), state import/export.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+#include "qap_swarm.h"
+
+using qap::InstDesc;
+
+namespace {
+
+struct Instance {
+    InstDesc d{};
+    int n = 0, m = 0, S = 0, P = 0;
+    int mul24 = 0;
+    int* order = nullptr;   // [m] migration ranking scratch
+    std::vector<void*> allocs;
+};
+
+}  // namespace
+
+struct qap_swarm {
+    std::vector<Instance> inst;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int engine = QAP_ENGINE_PLAIN;
+    int sticky = QAP_OK;
+    int grid_gd = 0;
+    int device = 0;
+    hipGraphExec_t graph = nullptr;
+    bool graph_ready = false;
+};
+
+namespace {
+
+int dev_err(qap_swarm* h, hipError_t e)
+{
+    if (e == hipSuccess) return QAP_OK;
+    if (h) h->sticky = QAP_ERR_DEVICE;
+    return e == hipErrorOutOfMemory ? QAP_ERR_NOMEM : QAP_ERR_DEVICE;
+}
+
+template <class T>
+hipError_t dalloc(Instance& I, T** p, size_t count)
+{
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+    if (e != hipSuccess) { *p = nullptr; return e; }
+    I.allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    return hipSuccess;
+}
+
+void free_instance(Instance& I)
+{
+    for (void* p : I.allocs) (void)hipFree(p);
+    I.allocs.clear();
+}
+
+int check_params(const qap_instance* in, const qap_params* p)
+{
+    if (!in || !p || !in->F || !in->D) return QAP_ERR_INVALID_ARG;
+    const int n = in->n;
+    if (n < 2 || n > qap::kMaxN) return QAP_ERR_INVALID_ARG;
+    if (p->num_swarms < 1 || p->particles_per_swarm < 1) return QAP_ERR_INVALID_ARG;
+    if ((long long)p->num_swarms * p->particles_per_swarm > (1LL << 24)) return QAP_ERR_INVALID_ARG;
+    const float cs[3] = {p->c1, p->c2, p->c3};
+    for (float c : cs)
+        if (!(c >= 0.0f && c <= 1.0f)) return QAP_ERR_INVALID_ARG;
+    if (!(p->vmax > 0.0f) || !(p->vmax < 1e30f)) return QAP_ERR_INVALID_ARG;
+    if (p->velocity_kernel != QAP_SV_RAW && p->velocity_kernel != QAP_SV_NORM) return QAP_ERR_INVALID_ARG;
+    if (p->st_depth < 0 || p->st_depth > n - 1) return QAP_ERR_INVALID_ARG;
+    if (p->mode != QAP_INDEPENDENT && p->mode != QAP_MIGRATION) return QAP_ERR_INVALID_ARG;
+    if (p->mode == QAP_MIGRATION) {
+        if (!(p->migration_factor >= 0.0f) || p->migration_period < 1) return QAP_ERR_INVALID_ARG;
+        const long long d = (long long)(p->migration_factor * (float)p->num_swarms);
+        if (2 * d >= p->num_swarms && d > 0) return QAP_ERR_INVALID_ARG;
+    }
+    if (p->local_search != 0 && p->local_search != 1) return QAP_ERR_INVALID_ARG;
+    if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_INT32) return QAP_ERR_INVALID_ARG;
+    if (p->engine != QAP_ENGINE_FUSED && p->engine != QAP_ENGINE_PLAIN) return QAP_ERR_INVALID_ARG;
+    return QAP_OK;
+}
+
+// Range check and path choice.  int8 MFMA needs every entry in [-128, 127];
+// any exact int32 contraction needs n * max|F| * max|D| < 2^31.
+int choose_path(const qap_instance* in, const qap_params* p, int engine, int* path, int* sym, int* mul24)
+{
+    const int n = in->n;
+    long long mf = 0, md = 0;
+    bool f8 = true, s = true;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const long long f = in->F[i * n + j], dd = in->D[i * n + j];
+            mf = std::max(mf, f < 0 ? -f : f);
+            md = std::max(md, dd < 0 ? -dd : dd);
+            if (f < -128 || f > 127 || dd < -128 || dd > 127) f8 = false;
+            if (in->F[i * n + j] != in->F[j * n + i] || in->D[i * n + j] != in->D[j * n + i]) s = false;
+        }
+    if ((long long)n * mf * md >= (1LL << 31)) return QAP_ERR_RANGE;
+    int pth;
+    if (p->delta_path == QAP_PATH_INT8_MFMA) {
+        if (!f8) return QAP_ERR_RANGE;
+        pth = 1;
+    } else if (p->delta_path == QAP_PATH_INT32) {
+        pth = 2;
+    } else {
+        pth = f8 ? 1 : 2;
+    }
+    if (engine == QAP_ENGINE_PLAIN) pth = 2;
+    *path = pth;
+    *sym = s ? 1 : 0;
+    *mul24 = (mf < (1LL << 23) && md < (1LL << 23)) ? 1 : 0;
+    return QAP_OK;
+}
+
+int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_params* p, int path, int sym,
+                   int mul24)
+{
+    const int n = in->n;
+    InstDesc& d = I.d;
+    I.n = n;
+    I.m = p->num_swarms;
+    I.S = p->particles_per_swarm;
+    I.P = I.m * I.S;
+    I.mul24 = mul24;
+    d.n = n;
+    d.npad = (n + 31) / 32 * 32;
+    d.m = I.m;
+    d.S = I.S;
+    d.P = I.P;
+    d.c1 = p->c1; d.c2 = p->c2; d.c3 = p->c3; d.vmax = p->vmax;
+    d.norm = p->velocity_kernel == QAP_SV_NORM;
+    d.depth = p->st_depth;
+    d.ls = p->local_search;
+    d.migrate = p->mode == QAP_MIGRATION;
+    d.migr_d = d.migrate ? (int)(p->migration_factor * (float)I.m) : 0;
+    d.period = p->migration_period < 1 ? 1 : p->migration_period;
+    d.sym = sym;
+    d.path = path;
+    d.seed = p->seed;
+    const size_t nn = (size_t)n * n, P = (size_t)I.P;
+    hipError_t e = hipSuccess;
+    int* F32 = nullptr; int* D32 = nullptr;
+#define TRY(x) do { e = (x); if (e != hipSuccess) return dev_err(nullptr, e); } while (0)
+    TRY(dalloc(I, &F32, nn));
+    TRY(dalloc(I, &D32, nn));
+    TRY(hipMemcpy(F32, in->F, nn * sizeof(int), hipMemcpyHostToDevice));
+    TRY(hipMemcpy(D32, in->D, nn * sizeof(int), hipMemcpyHostToDevice));
+    d.F32 = F32; d.D32 = D32;
+    if (path == 1) {
+        const size_t np = (size_t)d.npad;
+        std::vector<int8_t> hF(np * np, 0), hD(np * np, 0), hFT(np * np, 0), hDT(np * np, 0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                hF[i * np + j] = (int8_t)in->F[i * n + j];
+                hD[i * np + j] = (int8_t)in->D[i * n + j];
+                hFT[j * np + i] = (int8_t)in->F[i * n + j];
+                hDT[j * np + i] = (int8_t)in->D[i * n + j];
+            }
+        int8_t *F8, *D8, *FT8, *DT8;
+        TRY(dalloc(I, &F8, np * np));
+        TRY(dalloc(I, &D8, np * np));
+        TRY(dalloc(I, &FT8, np * np));
+        TRY(dalloc(I, &DT8, np * np));
+        TRY(hipMemcpy(F8, hF.data(), np * np, hipMemcpyHostToDevice));
+        TRY(hipMemcpy(D8, hD.data(), np * np, hipMemcpyHostToDevice));
+        TRY(hipMemcpy(FT8, hFT.data(), np * np, hipMemcpyHostToDevice));
+        TRY(hipMemcpy(DT8, hDT.data(), np * np, hipMemcpyHostToDevice));
+        d.F8 = F8; d.D8 = D8; d.FT8 = FT8; d.DT8 = DT8;
+    }
+    TRY(dalloc(I, &d.V[0], P * nn));
+    TRY(dalloc(I, &d.V[1], P * nn));
+    TRY(dalloc(I, &d.X[0], P * n));
+    TRY(dalloc(I, &d.X[1], P * n));
+    TRY(dalloc(I, &d.PL, P * n));
+    TRY(dalloc(I, &d.Xnew, P * n));
+    TRY(hipMemset(d.Xnew, 0, P * n));
+    TRY(dalloc(I, &d.goal, P));
+    TRY(dalloc(I, &d.goalPL, P));
+    TRY(dalloc(I, &d.PG, (size_t)I.m * n));
+    TRY(dalloc(I, &d.goalPG, (size_t)I.m));
+    TRY(dalloc(I, &d.smin, (size_t)I.m));
+    TRY(dalloc(I, &d.best, 1));
+    TRY(dalloc(I, &d.iter, 1));
+    TRY(dalloc(I, &I.order, (size_t)I.m));
+    TRY(dalloc(I, &d.scratch, (size_t)h->grid_gd * nn * (sym ? 1 : 2)));
+    // iteration 0
+    std::vector<long long> big((size_t)I.m, LLONG_MAX);
+    TRY(hipMemcpy(d.goalPG, big.data(), sizeof(long long) * I.m, hipMemcpyHostToDevice));
+    qap::BestRec br;
+    std::memset(&br, 0, sizeof br);
+    br.goal = LLONG_MAX;
+    TRY(hipMemcpy(d.best, &br, sizeof br, hipMemcpyHostToDevice));
+    const int zero = 0;
+    TRY(hipMemcpy(d.iter, &zero, sizeof zero, hipMemcpyHostToDevice));
+    TRY(qap::launch_init(d, h->stream));
+    TRY(qap::launch_goal_delta_i32(d, mul24, h->grid_gd, d.X[0], I.P, 2, nullptr, nullptr, h->stream));
+    TRY(qap::launch_bests(d, 1, I.order, h->stream));
+    TRY(hipStreamSynchronize(h->stream));
+#undef TRY
+    return QAP_OK;
+}
+
+int enqueue_iteration(qap_swarm* h)
+{
+    for (Instance& I : h->inst) {
+        hipError_t e;
+        if (h->engine == QAP_ENGINE_PLAIN)
+            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream);
+        else
+            e = qap::launch_fused_step(I.d, I.order, h->stream);
+        if (e != hipSuccess) return dev_err(h, e);
+    }
+    return QAP_OK;
+}
+
+int get_instance(qap_swarm* h, int32_t k, Instance** out)
+{
+    if (!h) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    if (k < 0 || k >= (int)h->inst.size()) return QAP_ERR_INVALID_ARG;
+    *out = &h->inst[(size_t)k];
+    return QAP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qap_swarm_strerror(int code)
+{
+    switch (code) {
+    case QAP_OK: return "ok";
+    case QAP_ERR_INVALID_ARG: return "invalid argument";
+    case QAP_ERR_RANGE: return "value range of F or D too wide for an exact contraction path";
+    case QAP_ERR_NOMEM: return "out of memory";
+    case QAP_ERR_DEVICE: return "device error";
+    case QAP_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+    }
+}
+
+void qap_swarm_destroy(qap_swarm* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (Instance& I : h->inst) free_instance(I);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count, qap_swarm** out)
+{
+    if (!out) return QAP_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!insts || !prms || count < 1) return QAP_ERR_INVALID_ARG;
+    // every host-side check comes before the first HIP call
+    std::vector<int> path((size_t)count), sym((size_t)count), mul24((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        int rc = check_params(&insts[k], &prms[k]);
+        if (rc != QAP_OK) return rc;
+        if (prms[k].engine != prms[0].engine) return QAP_ERR_INVALID_ARG;
+        rc = choose_path(&insts[k], &prms[k], prms[0].engine, &path[(size_t)k], &sym[(size_t)k], &mul24[(size_t)k]);
+        if (rc != QAP_OK) return rc;
+        if (prms[k].engine == QAP_ENGINE_FUSED) return QAP_ERR_UNSUPPORTED;
+    }
+    qap_swarm* h = new (std::nothrow) qap_swarm();
+    if (!h) return QAP_ERR_NOMEM;
+    h->engine = prms[0].engine;
+    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return QAP_ERR_DEVICE; }
+    if (prms[0].stream) {
+        h->stream = (hipStream_t)prms[0].stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) { delete h; return QAP_ERR_DEVICE; }
+        h->own_stream = true;
+    }
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    h->grid_gd = std::max(64, cus * 8);
+    h->inst.resize((size_t)count);
+    for (int k = 0; k < count; ++k) {
+        const int rc = setup_instance(h, h->inst[(size_t)k], &insts[k], &prms[k], path[(size_t)k], sym[(size_t)k],
+                                      mul24[(size_t)k]);
+        if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
+    }
+    *out = h;
+    return QAP_OK;
+}
+
+int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out)
+{
+    return qap_swarm_init_batch(inst, prm, 1, out);
+}
+
+int qap_swarm_step(qap_swarm* h, int32_t iterations)
+{
+    if (!h || iterations < 0) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    for (int it = 0; it < iterations; ++it) {
+        const int rc = enqueue_iteration(h);
+        if (rc != QAP_OK) return rc;
+    }
+    return QAP_OK;
+}
+
+int qap_swarm_sync(qap_swarm* h)
+{
+    if (!h) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    return dev_err(h, hipStreamSynchronize(h->stream));
+}
+
+int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    qap::BestRec br;
+    hipError_t e = hipMemcpyAsync(&br, I->d.best, sizeof br, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_err(h, e);
+    if (goal) *goal = br.goal;
+    if (iter_found) *iter_found = br.iter;
+    if (perm)
+        for (int j = 0; j < I->n; ++j) perm[j] = br.perm[j];
+    return QAP_OK;
+}
+
+int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!goals) return QAP_ERR_INVALID_ARG;
+    hipError_t e = hipMemcpyAsync(goals, I->d.goalPG, sizeof(long long) * I->m, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(h, e);
+}
+
+int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!st) return QAP_ERR_INVALID_ARG;
+    const InstDesc& d = I->d;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    int t = 0;
+    if (e == hipSuccess) e = hipMemcpy(&t, d.iter, sizeof t, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_err(h, e);
+    const int cur = t & 1;
+    const size_t n = (size_t)I->n, P = (size_t)I->P, m = (size_t)I->m;
+    std::vector<uint8_t> buf(std::max(P, m) * n);
+    auto perms_out = [&](const uint8_t* src, size_t rows, int32_t* dst) -> hipError_t {
+        hipError_t ee = hipMemcpy(buf.data(), src, rows * n, hipMemcpyDeviceToHost);
+        if (ee == hipSuccess)
+            for (size_t i = 0; i < rows * n; ++i) dst[i] = buf[i];
+        return ee;
+    };
+    if (e == hipSuccess && st->V) e = hipMemcpy(st->V, d.V[cur], P * n * n * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->X) e = perms_out(d.X[cur], P, st->X);
+    if (e == hipSuccess && st->PL) e = perms_out(d.PL, P, st->PL);
+    if (e == hipSuccess && st->goal) e = hipMemcpy(st->goal, d.goal, P * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->goalPL) e = hipMemcpy(st->goalPL, d.goalPL, P * 8, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->PG) e = perms_out(d.PG, m, st->PG);
+    if (e == hipSuccess && st->goalPG) e = hipMemcpy(st->goalPG, d.goalPG, m * 8, hipMemcpyDeviceToHost);
+    qap::BestRec br;
+    if (e == hipSuccess) e = hipMemcpy(&br, d.best, sizeof br, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_err(h, e);
+    st->best_goal = br.goal;
+    st->best_iter = br.iter;
+    st->best_swarm = br.swarm;
+    st->best_particle = br.member;
+    if (st->best_perm)
+        for (size_t j = 0; j < n; ++j) st->best_perm[j] = br.perm[j];
+    st->iteration = t;
+    return QAP_OK;
+}
+
+int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!st || !st->V || !st->X || !st->PL || !st->goal || !st->goalPL || !st->PG || !st->goalPG ||
+        !st->best_perm || st->iteration < 0)
+        return QAP_ERR_INVALID_ARG;
+    const InstDesc& d = I->d;
+    const size_t n = (size_t)I->n, P = (size_t)I->P, m = (size_t)I->m;
+    auto valid = [&](const int32_t* p, size_t rows) {
+        std::vector<char> seen(n);
+        for (size_t r = 0; r < rows; ++r) {
+            std::fill(seen.begin(), seen.end(), 0);
+            for (size_t j = 0; j < n; ++j) {
+                const int32_t v = p[r * n + j];
+                if (v < 0 || (size_t)v >= n || seen[(size_t)v]) return false;
+                seen[(size_t)v] = 1;
+            }
+        }
+        return true;
+    };
+    if (!valid(st->X, P) || !valid(st->PL, P) || !valid(st->PG, m) || !valid(st->best_perm, 1))
+        return QAP_ERR_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    const int t = st->iteration, cur = t & 1;
+    std::vector<uint8_t> buf(std::max(P, m) * n);
+    auto perms_in = [&](const int32_t* src, size_t rows, uint8_t* dst) -> hipError_t {
+        for (size_t i = 0; i < rows * n; ++i) buf[i] = (uint8_t)src[i];
+        return hipMemcpy(dst, buf.data(), rows * n, hipMemcpyHostToDevice);
+    };
+    if (e == hipSuccess) e = hipMemcpy(d.V[cur], st->V, P * n * n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = perms_in(st->X, P, d.X[cur]);
+    if (e == hipSuccess) e = perms_in(st->PL, P, d.PL);
+    if (e == hipSuccess) e = hipMemcpy(d.goal, st->goal, P * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.goalPL, st->goalPL, P * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = perms_in(st->PG, m, d.PG);
+    if (e == hipSuccess) e = hipMemcpy(d.goalPG, st->goalPG, m * 8, hipMemcpyHostToDevice);
+    qap::BestRec br;
+    std::memset(&br, 0, sizeof br);
+    br.goal = st->best_goal;
+    br.iter = st->best_iter;
+    br.swarm = st->best_swarm;
+    br.member = st->best_particle;
+    for (size_t j = 0; j < n; ++j) br.perm[j] = (uint8_t)st->best_perm[j];
+    if (e == hipSuccess) e = hipMemcpy(d.best, &br, sizeof br, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.iter, &t, sizeof t, hipMemcpyHostToDevice);
+    return dev_err(h, e);
+}
+
+int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count, int64_t* goals,
+                   int64_t* deltas)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!perms || !goals || count < 0) return QAP_ERR_INVALID_ARG;
+    if (count == 0) return QAP_OK;
+    const size_t n = (size_t)I->n;
+    std::vector<uint8_t> hp((size_t)count * n);
+    std::vector<char> seen(n);
+    for (int r = 0; r < count; ++r) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (size_t j = 0; j < n; ++j) {
+            const int32_t v = perms[(size_t)r * n + j];
+            if (v < 0 || (size_t)v >= n || seen[(size_t)v]) return QAP_ERR_INVALID_ARG;
+            seen[(size_t)v] = 1;
+            hp[(size_t)r * n + j] = (uint8_t)v;
+        }
+    }
+    uint8_t* dp = nullptr;
+    long long* dg = nullptr;
+    long long* dd = nullptr;
+    hipError_t e = hipMalloc(&dp, hp.size());
+    if (e == hipSuccess) e = hipMalloc(&dg, sizeof(long long) * (size_t)count);
+    if (e == hipSuccess && deltas) e = hipMalloc(&dd, sizeof(long long) * (size_t)count * n * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size(), hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess) {
+        if (I->d.path == 1)
+            e = qap::launch_eval_mfma(I->d, dp, count, dg, dd, h->stream);
+        else
+            e = qap::launch_goal_delta_i32(I->d, I->mul24, h->grid_gd, dp, count, 1, dg, dd, h->stream);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(goals, dg, sizeof(long long) * (size_t)count, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess && deltas)
+        e = hipMemcpyAsync(deltas, dd, sizeof(long long) * (size_t)count * n * n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (dp) (void)hipFree(dp);
+    if (dg) (void)hipFree(dg);
+    if (dd) (void)hipFree(dd);
+    return dev_err(h, e);
+}
+
+int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (delta_path) *delta_path = I->d.path == 1 ? QAP_PATH_INT8_MFMA : QAP_PATH_INT32;
+    if (symmetric) *symmetric = I->d.sym;
+    return QAP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,238 @@
+// S_x = SecondTarget (Alg. 1 of the paper) for one particle on one wave64.
+//
+// Input: the particle's V(t) (global, [n][n], row = location, column =
+// facility) and its solution z = X(t).  Keys are W = X + V in binary32: a cell
+// of Z has key 1 + v, every other cell v.  Selection i = 0 .. n-1 takes the
+// maximum key over the remaining rows and columns, leaving out the cells of
+// Z while i < depth; exact ties are broken by the k-th tied cell in
+// column-major order, k = bounded(stream word 4 + i, number of tied cells).
+//
+// Work layout: lane l owns columns l, l + 64, ... (CPL of them).  Per column
+// it keeps the Z cell's key and a cache of the best non-Z key over the alive
+// rows (value, first row, count).  The cache is an upper bound once one of
+// its rows may have gone ("stale"); it is recomputed by the whole wave
+// (one coalesced-by-lane column read) only when a selection actually needs
+// the exact value: always before depth, and afterwards only when the Z cell
+// is gone or does not beat the bound.  A selection is then one wave max plus
+// a ballot, O(n) per particle-iteration instead of the O(n^2) rescans of the
+// plain procedure.
+#pragma once
+#include "common.hpp"
+#include "philox.hpp"
+
+namespace qap {
+
+template <int CPL>
+struct StState {
+    float zk[CPL];   // key of the Z cell (1 + v)
+    int zr[CPL];     // row of the Z cell
+    bool zal[CPL];   // Z row still alive
+    float nzv[CPL];  // best non-Z key over alive rows (upper bound if stale)
+    int nzr[CPL];    // first row holding nzv (valid if !stale)
+    int nzc[CPL];    // number of alive non-Z rows holding nzv (valid if !stale)
+    bool stale[CPL];
+    bool cal[CPL];   // column not yet assigned
+    unsigned rowbits;  // bit j: row lane + 64 j alive
+};
+
+// Exact best non-Z key of column c over the alive rows (whole wave).
+template <int CPL>
+__device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, int c, int zr, unsigned rowbits,
+                                          float& mv, int& mr, int& mc)
+{
+    const int l = lane_id();
+    float v[CPL];
+    bool ok[CPL];
+    float best = -INFINITY;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int r = l + kWave * j;
+        ok[j] = (r < n) && ((rowbits >> j) & 1u) && (r != zr);
+        v[j] = ok[j] ? V[(size_t)r * n + c] : -INFINITY;
+        best = fmaxf(best, v[j]);
+    }
+    const float m = wave_max(best);
+    int cnt = 0, first = -1;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const uint64_t b = ballot64(ok[j] && v[j] == m);
+        cnt += __popcll(b);
+        if (first < 0 && b) first = kWave * j + __ffsll((long long)b) - 1;
+    }
+    mv = m;
+    mr = first;
+    mc = cnt;
+}
+
+// Row of the k-th tied cell (ascending row) of column c with key m.
+template <int CPL>
+__device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ V, int c, int zr, bool withZ,
+                                               unsigned rowbits, float m, int k)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int r = l + kWave * j;
+        bool ok = (r < n) && ((rowbits >> j) & 1u) && (withZ || r != zr);
+        float key = -INFINITY;
+        if (ok) {
+            const float v = V[(size_t)r * n + c];
+            key = (r == zr) ? 1.0f + v : v;
+        }
+        const uint64_t b = ballot64(ok && key == m);
+        const int pc = __popcll(b);
+        if (k < pc) {
+            const uint64_t below = b & ((l == 0) ? 0ull : (~0ull >> (64 - l)));
+            const bool mine = ((b >> l) & 1ull) && (__popcll(below) == k);
+            const uint64_t w = ballot64(mine);
+            return kWave * j + __ffsll((long long)w) - 1;
+        }
+        k -= pc;
+    }
+    return -1;  // unreachable when the counts are consistent
+}
+
+// Initial per-column cache by a full scan of V (exact, not stale).
+template <int CPL>
+__device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V, const uint8_t* __restrict__ z,
+                                             StState<CPL>& s)
+{
+    const int l = lane_id();
+    s.rowbits = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+        if (l + kWave * j < n) s.rowbits |= 1u << j;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int c = l + kWave * k;
+        s.cal[k] = c < n;
+        s.zr[k] = c < n ? (int)z[c] : -1;
+        s.zal[k] = c < n;
+        s.zk[k] = -INFINITY;
+        s.nzv[k] = -INFINITY;
+        s.nzr[k] = -1;
+        s.nzc[k] = 0;
+        s.stale[k] = false;
+    }
+    for (int r = 0; r < n; ++r) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const int c = l + kWave * k;
+            if (c < n) {
+                const float v = V[(size_t)r * n + c];
+                if (r == s.zr[k]) {
+                    s.zk[k] = 1.0f + v;
+                } else if (v > s.nzv[k]) {
+                    s.nzv[k] = v; s.nzr[k] = r; s.nzc[k] = 1;
+                } else if (v == s.nzv[k]) {
+                    s.nzc[k] += 1;
+                }
+            }
+        }
+    }
+}
+
+// Run the n selections.  Writes out[c] = chosen row for every column c < n.
+template <int CPL>
+__device__ void st_select(int n, int depth, const float* __restrict__ V, StState<CPL>& s, uint8_t* out,
+                          uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm)
+{
+    const int l = lane_id();
+    for (int i = 0; i < n; ++i) {
+        const bool skipZ = i < depth;
+        // 1. exact caches where this selection needs them
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const bool need = s.cal[k] && s.stale[k] && (skipZ || !s.zal[k] || !(s.zk[k] > s.nzv[k]));
+            uint64_t b = ballot64(need);
+            while (b) {
+                const int owner = __ffsll((long long)b) - 1;
+                b &= b - 1;
+                const int c = owner + kWave * k;
+                const int zr = readlane_i32(s.zr[k], owner);
+                float mv; int mr, mc;
+                st_rescan<CPL>(n, V, c, zr, s.rowbits, mv, mr, mc);
+                if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
+            }
+        }
+        // 2. per-column candidate (value, count, first row)
+        float cv[CPL];
+        int cc[CPL], cr[CPL];
+        float lbest = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            float v = s.nzv[k];
+            int cnt = s.nzc[k], row = s.nzr[k];
+            if (!skipZ && s.zal[k]) {
+                if (s.zk[k] > s.nzv[k]) { v = s.zk[k]; cnt = 1; row = s.zr[k]; }
+                else if (s.zk[k] == s.nzv[k]) { cnt += 1; row = min(row, s.zr[k]); }
+            }
+            if (!s.cal[k] || cnt == 0) v = -INFINITY;
+            cv[k] = v; cc[k] = cnt; cr[k] = row;
+            lbest = fmaxf(lbest, v);
+        }
+        const float m = wave_max(lbest);
+        // 3. tied columns
+        uint64_t bal[CPL];
+        int ncols = 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            bal[k] = ballot64(cv[k] == m && cv[k] != -INFINITY);
+            ncols += __popcll(bal[k]);
+        }
+        int selc = -1, selr = -1;
+        if (ncols == 1) {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+                if (bal[k]) {
+                    const int owner = __ffsll((long long)bal[k]) - 1;
+                    if (readlane_i32(cc[k], owner) == 1) {
+                        selc = owner + kWave * k;
+                        selr = readlane_i32(cr[k], owner);
+                    }
+                }
+        }
+        if (selc < 0) {
+            // general tie: |M| cells, pick the k-th in column-major order
+            int mycnt = 0;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) mycnt += ((bal[k] >> l) & 1ull) ? cc[k] : 0;
+            const int total = wave_sum_i32(mycnt);
+            const uint32_t w = stream_word(seed, 4u + (uint32_t)i, iter, member, swarm);
+            int kk = (int)bounded_u32(w, (uint32_t)total);
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                if (selc >= 0) break;
+                const int x = ((bal[k] >> l) & 1ull) ? cc[k] : 0;
+                const int incl = wave_incl_scan_i32(x);
+                const int tot = readlane_i32(incl, 63);
+                if (kk < tot) {
+                    const uint64_t hit = ballot64(incl > kk && x > 0 && incl - x <= kk);
+                    const int owner = __ffsll((long long)hit) - 1;
+                    const int before = readlane_i32(incl - x, owner);
+                    const int c = owner + kWave * k;
+                    const int zr = readlane_i32(s.zr[k], owner);
+                    const bool withZ = !skipZ && readlane_i32((int)s.zal[k], owner);
+                    selc = c;
+                    selr = st_kth_tied_row<CPL>(n, V, c, zr, withZ, s.rowbits, m, kk - before);
+                } else {
+                    kk -= tot;
+                }
+            }
+        }
+        // 4. apply the selection (a failed selection leaves the slot untouched)
+        if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
+        if (l == (selc & 63)) out[selc] = (uint8_t)selr;
+        if (l == (selr & 63)) s.rowbits &= ~(1u << (selr >> 6));
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            if (selc == l + kWave * k) s.cal[k] = false;
+            if (s.cal[k]) {
+                if (s.zr[k] == selr) s.zal[k] = false;
+                if (!s.stale[k] && (s.nzr[k] == selr || s.nzc[k] > 1)) s.stale[k] = true;
+            }
+        }
+    }
+}
+
+}  // namespace qap

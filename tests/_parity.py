@@ -1,0 +1,52 @@
+"""Helpers shared by the GPU parity tests (GPU library vs CPU oracle)."""
+import numpy as np
+
+VTOL = 1e-5  # FP32 velocities vs the FP64 oracle, relative to each column's largest entry
+
+
+def run_cfg(**kw):
+    """Parameter dict accepted by both paper_1504_05158_amd.make_params and OracleSwarm."""
+    base = dict(num_swarms=2, particles_per_swarm=8, c1=0.8, c2=0.5, c3=0.5, vmax=1.0, norm=True, depth=2,
+                local_search=True, migration=False, migration_factor=0.0, migration_period=1, seed=1)
+    base.update(kw)
+    return base
+
+
+def oracle_cfg(cfg):
+    return {k: v for k, v in cfg.items() if k not in ("engine", "delta_path")}
+
+
+def make_gpu(q, F, D, cfg):
+    return q.Swarm.create(F, D, **cfg)
+
+
+def oracle_from_state(orc, F, D, cfg, st):
+    o = orc.OracleSwarm(F, D, **oracle_cfg(cfg))
+    o.load_state(dict(st, V=np.asarray(st["V"], np.float64)))
+    return o
+
+
+def assert_v_close(Vg, Vo, tol=VTOL):
+    Vg = np.asarray(Vg, np.float64)
+    colmax = np.abs(Vo).max(axis=1, keepdims=True)  # [P, 1, n]: per column (facility)
+    err = np.abs(Vg - Vo)
+    bad = err > tol * colmax + 1e-30
+    if bad.any():
+        i = np.argwhere(bad)[0]
+        raise AssertionError("V mismatch at %s: gpu %r oracle %r (col max %r), %d cells" % (
+            tuple(i), Vg[tuple(i)], Vo[tuple(i)], colmax[i[0], 0, i[2]], int(bad.sum())))
+
+
+def assert_states_equal(g, o, vtol=VTOL, what=""):
+    """Everything integer is exact; V within vtol."""
+    for k in ("X", "PL", "goal", "goalPL", "PG", "goalPG", "best_perm"):
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        if not np.array_equal(a, b):
+            idx = np.argwhere(a != b)[0] if a.shape == b.shape else None
+            raise AssertionError("%s %s differs (first at %s): gpu %s oracle %s" % (
+                what, k, idx, a[tuple(idx[:1])] if idx is not None else a.shape,
+                b[tuple(idx[:1])] if idx is not None else b.shape))
+    assert int(g["best_goal"]) == int(o["best_goal"]), (what, g["best_goal"], o["best_goal"])
+    assert list(np.asarray(g["best_info"])) == list(np.asarray(o["best_info"])), (what, g["best_info"], o["best_info"])
+    assert int(g["t"]) == int(o["t"])
+    assert_v_close(g["V"], o["V"], vtol)
