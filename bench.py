@@ -1,0 +1,180 @@
+#!/usr/bin/env python
+"""Throughput of the multi-swarm PSO hot path for the QAP on one MI355X.
+
+Workload (the headline configuration): n = 128, F and D symmetric integers
+uniform in [0, 127] with zero diagonal (seeded, synthetic -- stands in for the
+paper's QAPLIB instances), 200 swarms x 50 particles = 10,000 particles,
+S_v = Norm, c1 = 0.8, c2 = c3 = 0.5, vmax = 1, SecondTarget depth 2, one
+pair-exchange improvement per particle-iteration, independent swarms.
+
+A step is one iteration of every particle (S_x, velocity, goal, pair-exchange
+deltas and exchange, P^L, swarm bests).  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+VALU_INT_PEAK_TOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 ops per multiply-add
+
+WORKLOAD = dict(name="n128x10k", n=128, seed_inst=104, num_swarms=200, particles_per_swarm=50)
+RUN = dict(c1=0.8, c2=0.5, c3=0.5, vmax=1.0, norm=True, depth=2, local_search=True, migration=False, seed=1)
+
+
+def algorithmic_bytes(stage: str, n: int) -> int:
+    """HBM bytes per particle-iteration the stage cannot avoid."""
+    if stage == "fused":      # V(t) read + V(t+1) write, X read+write, P^L read, goal + P^L goal
+        return 8 * n * n + 3 * n + 24
+    if stage == "sx":         # V(t) read, X(t) read, X' write
+        return 4 * n * n + 2 * n
+    if stage == "velocity":   # V(t) read + V(t+1) write, X, P^L, P^G reads
+        return 8 * n * n + 3 * n
+    if stage == "goal_delta":  # X' read, X write, P^L read, goal, P^L goal
+        return 3 * n + 24
+    return 0
+
+
+def contraction_ops(n: int, sym: bool) -> int:
+    """Integer operations of the pair-exchange contraction per particle (2 per multiply-add)."""
+    return 2 * n ** 3 * (1 if sym else 2)
+
+
+def run_gpu(args, engine: str):
+    import numpy as np
+    import torch
+    import paper_1504_05158_amd as q
+    import qap_inputs as gen
+
+    n = WORKLOAD["n"]
+    F, D = gen.uniform_instance(n, 0, 127, WORKLOAD["seed_inst"])
+    stream = torch.cuda.Stream()
+    sw = q.Swarm.create(F, D, stream=stream, engine=engine, num_swarms=WORKLOAD["num_swarms"],
+                        particles_per_swarm=WORKLOAD["particles_per_swarm"], **RUN)
+    P = WORKLOAD["num_swarms"] * WORKLOAD["particles_per_swarm"]
+    path, sym = sw.path()
+    sw.step(args.warmup)
+    sw.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sw.step(args.steps)
+    sw.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    value = P * args.steps / secs
+    # per-kernel durations from HIP events on the handle's stream, over a second timed pass
+    sw.profile(True)
+    sw.step(args.steps)
+    stage_ms, iters = sw.profile(False)
+    best = sw.best()[0]
+    sw.close()
+    dom = max(stage_ms, key=stage_ms.get)
+    avg_ms = stage_ms[dom] / max(iters, 1)
+    if dom == "goal_delta" and engine == "plain":
+        achieved = contraction_ops(n, sym) * P / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=round(achieved, 3), peak=VALU_INT_PEAK_TOPS, unit="TOP/s",
+                    frac=round(achieved / VALU_INT_PEAK_TOPS, 4), traffic=None)
+    else:
+        bpl = algorithmic_bytes(dom, n) * P
+        achieved = bpl / (avg_ms * 1e-3) / 1e9
+        roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+    roof["kernel"] = dom
+    roof["avg_ms"] = round(avg_ms, 4)
+    return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, roofline=roof,
+                stage_ms={k: round(v / max(iters, 1), 4) for k, v in stage_ms.items()}, best=best)
+
+
+def cpu_baseline(target_s: float = 12.0):
+    """The oracle, as it stands, on a bounded sample of the same workload."""
+    import oracle as orc
+    import qap_inputs as gen
+
+    n = WORKLOAD["n"]
+    F, D = gen.uniform_instance(n, 0, 127, WORKLOAD["seed_inst"])
+    threads = max(1, min(16, os.cpu_count() or 1))
+    orc.set_threads(threads)
+    used = orc.get_threads()
+    per = WORKLOAD["particles_per_swarm"]
+    # calibrate on one swarm, then size the sample to about target_s of work
+    sw = orc.OracleSwarm(F, D, num_swarms=1, particles_per_swarm=per, **RUN)
+    t0 = time.perf_counter()
+    sw.step(1)
+    dt = time.perf_counter() - t0
+    swarms = max(1, min(WORKLOAD["num_swarms"], int(target_s / max(dt, 1e-3) / 2)))
+    sw = orc.OracleSwarm(F, D, num_swarms=swarms, particles_per_swarm=per, **RUN)
+    steps = 2
+    t0 = time.perf_counter()
+    sw.step(steps)
+    secs = time.perf_counter() - t0
+    return dict(value=round(swarms * per * steps / secs, 2), unit="particle-iterations/s", cores=used,
+                kind="oracle",
+                sample="%d swarms x %d particles (of 200 x 50), %d iterations, n=128, %d OpenMP threads, %.1f s"
+                       % (swarms, per, steps, used, secs))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--engine", default="plain", choices=["fused", "plain"])
+    ap.add_argument("--compare", action="store_true", help="also time the other engine")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
+              "(the swarms would shard by swarm across GPUs, which is not built); use --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    res = run_gpu(args, args.engine)
+    other = None
+    if args.compare:
+        oth = "plain" if args.engine == "fused" else "fused"
+        try:
+            other = run_gpu(args, oth)
+        except Exception as e:  # the other engine may be unavailable for this build
+            other = dict(error=str(e))
+    line = {
+        "metric": "particle-iterations/sec at n=128, 10k particles (batched int8 vs plain path)",
+        "value": round(res["value"], 1),
+        "unit": "particle-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+i8" if res["path"] == "int8" else "f32+i32",
+        "data": "synthetic",
+        "config": {"workload": "n128x10k: n=128 QAP, F and D symmetric U{0..127}, 200 swarms x 50 particles, "
+                               "Norm, c=(0.8,0.5,0.5), depth 2, one pair exchange",
+                   "n": WORKLOAD["n"], "particles": res["P"], "engine": args.engine, "delta_path": res["path"],
+                   "parallelism": "single GPU"},
+        "roofline": res["roofline"],
+        "stage_ms": res["stage_ms"],
+    }
+    if other is not None:
+        line["compare"] = {("plain" if args.engine == "fused" else "fused"):
+                           (round(other["value"], 1) if "value" in other else other)}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,20 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
  * *delta_path, and 1 in *symmetric if F and D are both symmetric. */
 int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric);
 
+/* Kernel timing for measurement.  enable = 1 switches the handle to
+ * profiled stepping: every later qap_swarm_step launches its kernels one by
+ * one (no graph) with HIP events recorded on the handle's stream around each
+ * stage kernel, and the counters restart from zero; enable = 0 switches back.
+ * stage_ms (QAP_NUM_STAGES doubles, may be NULL) receives the summed kernel
+ * time per stage and *launches the number of iterations profiled (waits
+ * first).  Stages: QAP_STAGE_SX (S_x), QAP_STAGE_VELOCITY,
+ * QAP_STAGE_GOAL_DELTA (goal, deltas, exchange, P^L), QAP_STAGE_FUSED (the
+ * whole particle iteration in one kernel), QAP_STAGE_BESTS (swarm bests,
+ * best-ever, migration). */
+enum { QAP_STAGE_SX = 0, QAP_STAGE_VELOCITY = 1, QAP_STAGE_GOAL_DELTA = 2, QAP_STAGE_FUSED = 3,
+       QAP_STAGE_BESTS = 4, QAP_NUM_STAGES = 5 };
+int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* launches);
+
 /* Release every device and host resource of the handle (NULL is a no-op). */
 void qap_swarm_destroy(qap_swarm* h);
 

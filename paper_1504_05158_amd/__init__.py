@@ -30,7 +30,8 @@ QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
 
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
-           "qap_swarm_path", "qap_swarm_destroy", "qap_swarm_strerror"]
+           "qap_swarm_path", "qap_swarm_profile", "qap_swarm_destroy", "qap_swarm_strerror"]
+STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
 class qap_instance(ctypes.Structure):
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_eval.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int64),
                                  P(ctypes.c_int64)]
     L.qap_swarm_path.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.qap_swarm_profile.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     L.qap_swarm_destroy.argtypes = [vp]
     L.qap_swarm_destroy.restype = None
     L.qap_swarm_strerror.argtypes = [ctypes.c_int]
@@ -268,3 +270,11 @@ class Swarm:
         s = ctypes.c_int32()
         _check(load_library().qap_swarm_path(self.h, instance, ctypes.byref(p), ctypes.byref(s)), "qap_swarm_path")
         return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32"}[p.value], bool(s.value)
+
+    def profile(self, enable: bool):
+        """Switch profiled stepping on/off; returns ({stage: ms}, iterations) so far."""
+        ms = np.zeros(len(STAGES), np.float64)
+        it = ctypes.c_int64()
+        _check(load_library().qap_swarm_profile(self.h, 1 if enable else 0, _ptr(ms, ctypes.c_double),
+                                                ctypes.byref(it)), "qap_swarm_profile")
+        return dict(zip(STAGES, ms.tolist())), int(it.value)

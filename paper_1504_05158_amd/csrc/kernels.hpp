@@ -9,8 +9,11 @@ namespace qap {
 hipError_t launch_init(const InstDesc& d, hipStream_t st);
 
 // Per-stage engine: one iteration of one instance (S_x, velocity,
-// goal + deltas + local search, swarm bests, finish).
-hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st);
+// goal + deltas + local search, swarm bests, finish).  If ev is not NULL,
+// events are recorded around the stages: ev[2s], ev[2s+1] for stage s
+// (0 S_x, 1 velocity, 2 goal/deltas, 4 bests).
+hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st,
+                             hipEvent_t* ev);
 
 // Goal (+ deltas) of `count` permutations [count][n] (device) on the int32 path.
 // mode 1: eval into goals/deltas; mode 2: initial goals of the particles.
@@ -21,7 +24,7 @@ hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, cons
 hipError_t launch_bests(const InstDesc& d, int init, int* order, hipStream_t st);
 
 // Fused engine: one iteration of one instance in one kernel, plus bests.
-hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st);
+hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipEvent_t* ev);
 
 // Goal (+ deltas) of `count` permutations on the int8 MFMA path (eval only).
 hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals,

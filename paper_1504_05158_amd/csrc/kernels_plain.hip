@@ -464,24 +464,38 @@ hipError_t launch_init(const InstDesc& d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st)
+hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st,
+                             hipEvent_t* ev)
 {
     const int cpl = (d.n + kWave - 1) / kWave;
     const dim3 gst(blocks_for(d.P, 4)), bst(256);
+    hipError_t e;
+#define REC(i) do { if (ev) { e = hipEventRecord(ev[i], st); if (e != hipSuccess) return e; } } while (0)
+    REC(0);
     switch (cpl) {
     case 1: hipLaunchKernelGGL(k_second_target<1>, gst, bst, 0, st, d); break;
     case 2: hipLaunchKernelGGL(k_second_target<2>, gst, bst, 0, st, d); break;
     case 3: hipLaunchKernelGGL(k_second_target<3>, gst, bst, 0, st, d); break;
     default: hipLaunchKernelGGL(k_second_target<4>, gst, bst, 0, st, d); break;
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
+    REC(1);
+    REC(2);
     hipLaunchKernelGGL(k_velocity, dim3(blocks_for((long long)d.P * d.n, 256)), dim3(256), 0, st, d);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    REC(3);
+    REC(4);
     e = launch_goal_delta_i32(d, mul24, grid_gd, d.Xnew, d.P, 0, nullptr, nullptr, st);
     if (e != hipSuccess) return e;
-    return launch_bests(d, 0, order, st);
+    REC(5);
+    REC(8);
+    e = launch_bests(d, 0, order, st);
+    if (e != hipSuccess) return e;
+    REC(9);
+#undef REC
+    return hipSuccess;
 }
 
 }  // namespace qap

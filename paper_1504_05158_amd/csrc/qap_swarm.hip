@@ -38,6 +38,12 @@ struct qap_swarm {
     int device = 0;
     hipGraphExec_t graph = nullptr;
     bool graph_ready = false;
+    // profiled stepping
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;   // 2 * QAP_NUM_STAGES per recorded iteration
+    size_t ev_used = 0;
+    double stage_ms[QAP_NUM_STAGES] = {};
+    long long prof_iters = 0;
 };
 
 namespace {
@@ -211,16 +217,59 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     return QAP_OK;
 }
 
+constexpr int kEvPerIter = 2 * QAP_NUM_STAGES;
+
+hipEvent_t* prof_events(qap_swarm* h)
+{
+    if (h->ev_used + kEvPerIter > h->ev_pool.size()) {
+        for (int i = 0; i < kEvPerIter; ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            h->ev_pool.push_back(e);
+        }
+    }
+    hipEvent_t* ev = h->ev_pool.data() + h->ev_used;
+    h->ev_used += kEvPerIter;
+    return ev;
+}
+
+// Fold the recorded event pairs into the per-stage totals.
+int prof_collect(qap_swarm* h)
+{
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_err(h, e);
+    for (size_t base = 0; base + kEvPerIter <= h->ev_used; base += kEvPerIter) {
+        for (int s = 0; s < QAP_NUM_STAGES; ++s) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, h->ev_pool[base + 2 * s], h->ev_pool[base + 2 * s + 1]) == hipSuccess)
+                h->stage_ms[s] += ms;
+        }
+    }
+    (void)hipGetLastError();  // stages an engine does not record leave unrecorded pairs
+    h->ev_used = 0;
+    return QAP_OK;
+}
+
 int enqueue_iteration(qap_swarm* h)
 {
     for (Instance& I : h->inst) {
         hipError_t e;
+        hipEvent_t* ev = nullptr;
+        if (h->profiling) {
+            if (h->ev_used + kEvPerIter > 4096) {
+                const int rc = prof_collect(h);
+                if (rc != QAP_OK) return rc;
+            }
+            ev = prof_events(h);
+            if (!ev) return dev_err(h, hipErrorOutOfMemory);
+        }
         if (h->engine == QAP_ENGINE_PLAIN)
-            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream);
+            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream, ev);
         else
-            e = qap::launch_fused_step(I.d, I.order, h->stream);
+            e = qap::launch_fused_step(I.d, I.order, h->stream, ev);
         if (e != hipSuccess) return dev_err(h, e);
     }
+    if (h->profiling) h->prof_iters += 1;
     return QAP_OK;
 }
 
@@ -255,6 +304,7 @@ void qap_swarm_destroy(qap_swarm* h)
     if (!h) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     for (Instance& I : h->inst) free_instance(I);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -479,6 +529,25 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
     if (dg) (void)hipFree(dg);
     if (dd) (void)hipFree(dd);
     return dev_err(h, e);
+}
+
+int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* launches)
+{
+    if (!h || (enable != 0 && enable != 1)) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    if (h->profiling) {
+        const int rc = prof_collect(h);
+        if (rc != QAP_OK) return rc;
+    }
+    if (stage_ms)
+        for (int s = 0; s < QAP_NUM_STAGES; ++s) stage_ms[s] = h->stage_ms[s];
+    if (launches) *launches = h->prof_iters;
+    if ((bool)enable != h->profiling) {
+        h->profiling = enable != 0;
+        for (double& v : h->stage_ms) v = 0.0;
+        h->prof_iters = 0;
+    }
+    return QAP_OK;
 }
 
 int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric)
