@@ -26,6 +26,9 @@ hipError_t launch_bests(const InstDesc& d, int init, int* order, hipStream_t st)
 // Fused engine: one iteration of one instance in one kernel, plus bests.
 hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipEvent_t* ev);
 
+// Whether the fused kernel covers an instance (int8 path, n <= 160).
+bool fused_supported(const InstDesc& d);
+
 // Goal (+ deltas) of `count` permutations on the int8 MFMA path (eval only).
 hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
                             long long* deltas, hipStream_t st);

@@ -1,13 +1,429 @@
-// Fused engine (one kernel per iteration, int8 MFMA contraction).
+// Fused engine: the whole particle iteration in one kernel, one wave64 per
+// particle, F and D staged in LDS as int8, the pair-exchange contraction on
+// gfx950 int8 MFMA (v_mfma_i32_32x32x32_i8, int32 accumulation).
+//
+// Per particle (wave):
+//  A. stream V(t) once, lane = column (facility), 64 columns per pass, the
+//     column held in registers: the velocity update of eq. (velocity) with S_v,
+//     the column norm, the store of V(t+1) (the other buffer), and the
+//     SecondTarget column caches (max key, Z-cell key).  The at most three
+//     cells per column touched by the attraction terms (rows of X, P^L, P^G)
+//     are corrected after the pass.
+//  B. SecondTarget (Alg. 1) on X(t) + V(t), rescans reading V(t) from L2.
+//  C. A = F . Dp^T and A^T = Dp . F^T (Dp[y][k] = D[p_y][p_k]) tile by tile
+//     on MFMA; goal = trace(A); for every pair x < y
+//       delta = 2 (A_xy + A_yx - A_xx - A_yy)
+//               + (2 f_xy - f_xx - f_yy)(2 Dp_xy - Dp_xx - Dp_yy)        (F, D symmetric)
+//     or, in general, with B = F^T . Dp' on (F^T, D^T):
+//       delta = A_xy + A_yx + B_xy + B_yx - (A_xx + B_xx) - (A_yy + B_yy) - kappa + lambda;
+//     the lexicographically first minimum (delta, x, y) is applied if < 0.
+//  D. X(t+1), goal, P^L.
 #include "kernels.hpp"
+#include "second_target.hpp"
 
 namespace qap {
 
-hipError_t launch_fused_step(const InstDesc&, int*, hipStream_t, hipEvent_t*) { return hipErrorNotSupported; }
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
-hipError_t launch_eval_mfma(const InstDesc&, const uint8_t*, int, long long*, long long*, hipStream_t)
+namespace {
+
+constexpr int kWaves = 4;  // particles (waves) per workgroup
+
+__device__ __forceinline__ void wave_sync()
 {
-    return hipErrorNotSupported;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 16 bytes Dm[py][p[kb + j]], j = 0..15, packed little-endian into 4 ints.
+__device__ __forceinline__ v4i gather16(const int8_t* Dm, int np, int py, const uint8_t* p, int kb)
+{
+    const v4i pk = *reinterpret_cast<const v4i*>(p + kb);
+    const uint8_t* row = reinterpret_cast<const uint8_t*>(Dm) + py * np;
+    v4i out;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t word = (uint32_t)pk[w];
+        uint32_t r = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) r |= (uint32_t)row[(word >> (8 * b)) & 0xffu] << (8 * b);
+        out[w] = (int)r;
+    }
+    return out;
+}
+
+__device__ __forceinline__ v4i frag16(const int8_t* M, int np, int row, int kb)
+{
+    return *reinterpret_cast<const v4i*>(M + row * np + kb);
+}
+
+__device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c)
+{
+    return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// acc element i of lane l in a 32x32 tile: row 8(i/4) + 4(l/32) + i%4, column l%32
+__device__ __forceinline__ int tile_row(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
+
+// Row info per index x: p_x, f_xx, Dp_xx, diagonal sum dA_x (A_xx, or A_xx + B_xx).
+struct RowInfo {
+    int p, f, dp, da;
+};
+
+// Stage C for one permutation held in LDS (sp, NP bytes, entries >= n are 0).
+// Returns the goal; bestkey = (delta << 16) | (x << 8) | y of the first
+// minimum pair (LLONG_MAX if n < 2).  If dout != NULL every delta is written.
+template <int NP, bool SYM>
+__device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const int8_t* sFT, const int8_t* sDT,
+                                const uint8_t* sp, RowInfo* sri, bool want_pairs, long long* dout,
+                                long long& goal, long long& bestkey)
+{
+    constexpr int T = NP / 32;
+    const int l = lane_id(), h = l >> 5, lc = l & 31;
+    // Dp (and Dp' for the general case) fragments for every (block, K chunk)
+    v4i dp[T][T];
+    v4i dpt[SYM ? 1 : T][SYM ? 1 : T];
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+        const int y = 32 * b + lc;
+        const int py = y < n ? (int)sp[y] : 0;
+#pragma unroll
+        for (int kc = 0; kc < T; ++kc) {
+            dp[b][kc] = y < n ? gather16(sD, NP, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            if constexpr (!SYM) dpt[b][kc] = y < n ? gather16(sDT, NP, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+        }
+    }
+    // diagonal tiles: A_xx (and B_xx) -> row info, goal = trace(A)
+    long long gsum = 0;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        v16i acc = {};
+        v16i accb = {};
+#pragma unroll
+        for (int kc = 0; kc < T; ++kc) {
+            acc = mfma32(frag16(sF, NP, 32 * a + lc, 32 * kc + 16 * h), dp[a][kc], acc);
+            if constexpr (!SYM) accb = mfma32(frag16(sFT, NP, 32 * a + lc, 32 * kc + 16 * h), dpt[a][kc], accb);
+        }
+        if (h == ((lc >> 2) & 1)) {
+            const int want = 4 * (lc >> 3) + (lc & 3);
+            int da = 0, db = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i == want) { da = acc[i]; if constexpr (!SYM) db = accb[i]; }
+            const int x = 32 * a + lc;
+            if (x < n) {
+                gsum += da;
+                const int px = sp[x];
+                RowInfo ri;
+                ri.p = px;
+                ri.f = sF[x * NP + x];
+                ri.dp = sD[px * NP + px];
+                ri.da = SYM ? 2 * da : da + db;
+                sri[x] = ri;
+            }
+        }
+    }
+    goal = wave_sum_i64(gsum);
+    bestkey = LLONG_MAX;
+    if (!want_pairs) return;
+    wave_sync();
+    // all tiles a <= b
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+#pragma unroll
+        for (int b = a; b < T; ++b) {
+            const int y = 32 * b + lc;
+            v16i A = {}, AT = {}, B = {}, BT = {};
+#pragma unroll
+            for (int kc = 0; kc < T; ++kc) {
+                const v4i fa = frag16(sF, NP, 32 * a + lc, 32 * kc + 16 * h);
+                const v4i fb = frag16(sF, NP, 32 * b + lc, 32 * kc + 16 * h);
+                A = mfma32(fa, dp[b][kc], A);     // A[x][y]  = sum_k F[x][k] Dp[y][k]
+                AT = mfma32(dp[a][kc], fb, AT);   // AT[x][y] = sum_k Dp[x][k] F[y][k] = A[y][x]
+                if constexpr (!SYM) {
+                    const v4i ga = frag16(sFT, NP, 32 * a + lc, 32 * kc + 16 * h);
+                    const v4i gb = frag16(sFT, NP, 32 * b + lc, 32 * kc + 16 * h);
+                    B = mfma32(ga, dpt[b][kc], B);
+                    BT = mfma32(dpt[a][kc], gb, BT);
+                }
+            }
+            if (y >= n) continue;
+            const RowInfo cy = sri[y];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int x = 32 * a + tile_row(i, h);
+                if (x >= y) continue;
+                const RowInfo rx = sri[x];
+                const int fxy = sF[x * NP + y];
+                const int dxy = sD[rx.p * NP + cy.p];
+                int del;
+                if constexpr (SYM) {
+                    del = 2 * (A[i] + AT[i]) - rx.da - cy.da + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
+                } else {
+                    const int fyx = sF[y * NP + x];
+                    const int dyx = sD[cy.p * NP + rx.p];
+                    const int faa = rx.f, fbb = cy.f, daa = rx.dp, dbb = cy.dp;
+                    const int kap = (faa - fyx) * (dyx - daa) + (fxy - fbb) * (dbb - dxy) + (faa - fxy) * (dxy - daa) +
+                                    (fyx - fbb) * (dbb - dyx);
+                    const int lam = (faa - fbb) * (dbb - daa) + (fxy - fyx) * (dyx - dxy);
+                    del = A[i] + AT[i] + B[i] + BT[i] - rx.da - cy.da - kap + lam;
+                }
+                if (dout) {
+                    dout[(size_t)x * n + y] = del;
+                    dout[(size_t)y * n + x] = del;
+                }
+                const long long key = ((long long)del << 16) | (x << 8) | y;
+                bestkey = key < bestkey ? key : bestkey;
+            }
+        }
+    }
+    // wave minimum
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const long long o = __shfl_xor(bestkey, off, kWave);
+        bestkey = o < bestkey ? o : bestkey;
+    }
+}
+
+template <int NP, bool SYM>
+__device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF, int8_t* sD, int8_t* sFT, int8_t* sDT)
+{
+    const int nv = NP * NP / 16;
+    const v4i* F = reinterpret_cast<const v4i*>(d.F8);
+    const v4i* D = reinterpret_cast<const v4i*>(d.D8);
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+        reinterpret_cast<v4i*>(sF)[i] = F[i];
+        reinterpret_cast<v4i*>(sD)[i] = D[i];
+        if constexpr (!SYM) {
+            reinterpret_cast<v4i*>(sFT)[i] = reinterpret_cast<const v4i*>(d.FT8)[i];
+            reinterpret_cast<v4i*>(sDT)[i] = reinterpret_cast<const v4i*>(d.DT8)[i];
+        }
+    }
+}
+
+__device__ __forceinline__ float clampv(float t, float vmax) { return fminf(fmaxf(t, -vmax), vmax); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ fused step
+template <int NP, bool SYM>
+__global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
+{
+    constexpr int CPL = (NP + kWave - 1) / kWave;
+    __shared__ __attribute__((aligned(16))) int8_t sF[NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
+    __shared__ RowInfo sri[kWaves][NP];
+    load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
+    __syncthreads();
+
+    const int w = threadIdx.x / kWave, l = lane_id();
+    const int k = blockIdx.x * kWaves + w;
+    if (k >= d.P) return;
+    const int n = d.n;
+    const int tprev = *d.iter;
+    const uint32_t tau = (uint32_t)tprev + 1u;
+    const int cur = tprev & 1;
+    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const float* Vp = d.V[cur] + (size_t)k * n * n;
+    float* Vq = d.V[cur ^ 1] + (size_t)k * n * n;
+    const uint8_t* Xk = d.X[cur] + (size_t)k * n;
+    const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
+    const float s2 = __fmul_rn(d.c2, unit_float(rb.w[0]));
+    const float s3 = __fmul_rn(d.c3, unit_float(rb.w[1]));
+    const float c1 = d.c1, vmax = d.vmax;
+
+    // ---- A. velocity stream + SecondTarget caches
+    StState<CPL> st;
+    st.rowbits = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+        if (l + kWave * j < n) st.rowbits |= 1u << j;
+#pragma unroll
+    for (int kk = 0; kk < CPL; ++kk) {
+        const int c = l + kWave * kk;
+        const bool on = c < n;
+        int xr = 0, lr = 0, gr = 0;
+        float vx = 0.0f, vl = 0.0f, vg = 0.0f;
+        if (on) {
+            xr = Xk[c];
+            lr = d.PL[(size_t)k * n + c];
+            gr = d.PG[(size_t)g * n + c];
+            vx = Vp[(size_t)xr * n + c];
+            vl = Vp[(size_t)lr * n + c];
+            vg = Vp[(size_t)gr * n + c];
+        }
+        float col[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) col[r] = (on && r < n) ? Vp[(size_t)r * n + c] : 0.0f;
+        float m = -INFINITY, sum = 0.0f;
+#pragma unroll
+        for (int r = 0; r < NP; ++r) {
+            if (r < n) {
+                m = fmaxf(m, col[r]);
+                const float t = clampv(__fmul_rn(c1, col[r]), vmax);
+                col[r] = t;
+                sum = __fadd_rn(sum, fabsf(t));
+            }
+        }
+        // the (at most three) cells with attraction terms
+        float tx, tl = 0.0f, tg = 0.0f;
+        {
+            const float ax = (float)((xr == lr) - 1), bx = (float)((xr == gr) - 1);
+            tx = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vx), __fmul_rn(s2, ax)), __fmul_rn(s3, bx)), vmax);
+            sum = __fadd_rn(sum, fabsf(tx) - fabsf(clampv(__fmul_rn(c1, vx), vmax)));
+        }
+        const bool dl = lr != xr, dg = gr != xr && gr != lr;
+        if (dl) {
+            const float bl = (float)(lr == gr);
+            tl = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vl), s2), __fmul_rn(s3, bl)), vmax);
+            sum = __fadd_rn(sum, fabsf(tl) - fabsf(clampv(__fmul_rn(c1, vl), vmax)));
+        }
+        if (dg) {
+            tg = clampv(__fadd_rn(__fmul_rn(c1, vg), s3), vmax);
+            sum = __fadd_rn(sum, fabsf(tg) - fabsf(clampv(__fmul_rn(c1, vg), vmax)));
+        }
+        const float inv = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < NP; ++r)
+                if (r < n) Vq[(size_t)r * n + c] = d.norm ? __fmul_rn(col[r], inv) : col[r];
+            // same lane, same address, later in program order: these stores win
+            Vq[(size_t)xr * n + c] = d.norm ? __fmul_rn(tx, inv) : tx;
+            if (dl) Vq[(size_t)lr * n + c] = d.norm ? __fmul_rn(tl, inv) : tl;
+            if (dg) Vq[(size_t)gr * n + c] = d.norm ? __fmul_rn(tg, inv) : tg;
+        }
+        st.cal[kk] = on;
+        st.zal[kk] = on;
+        st.zr[kk] = on ? xr : -1;
+        st.zk[kk] = on ? 1.0f + vx : -INFINITY;
+        st.nzv[kk] = on ? m : -INFINITY;  // upper bound of the non-Z keys
+        st.nzr[kk] = -1;
+        st.nzc[kk] = 0;
+        st.stale[kk] = on;
+    }
+
+    // ---- B. SecondTarget
+    uint8_t* pw = sp[w];
+    for (int j = n + l; j < NP; j += kWave) pw[j] = 0;
+    st_select<CPL>(n, d.depth, Vp, st, pw, d.seed, tau, s, g);
+    wave_sync();
+
+    // ---- C. goal, pair-exchange deltas, one exchange
+    long long goal, key;
+    goal_delta_mfma<NP, SYM>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
+    int ba = -1, bb = -1;
+    if (d.ls && key != LLONG_MAX) {
+        const long long del = key >> 16;
+        if (del < 0) {
+            ba = (int)((key >> 8) & 0xff);
+            bb = (int)(key & 0xff);
+            goal += del;
+        }
+    }
+
+    // ---- D. X(t+1), goal, P^L
+    uint8_t* Xo = d.X[cur ^ 1] + (size_t)k * n;
+    const bool improve = goal < d.goalPL[k];
+    for (int j = l; j < n; j += kWave) {
+        uint8_t v = pw[j];
+        if (j == ba) v = pw[bb];
+        if (j == bb) v = pw[ba];
+        Xo[j] = v;
+        if (improve) d.PL[(size_t)k * n + j] = v;
+    }
+    if (l == 0) {
+        d.goal[k] = goal;
+        if (improve) d.goalPL[k] = goal;
+    }
+}
+
+// ------------------------------------------------------------------ eval
+template <int NP, bool SYM>
+__global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __restrict__ perms, int count,
+                                                   long long* __restrict__ goals, long long* __restrict__ deltas)
+{
+    __shared__ __attribute__((aligned(16))) int8_t sF[NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
+    __shared__ RowInfo sri[kWaves][NP];
+    load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
+    __syncthreads();
+    const int w = threadIdx.x / kWave, l = lane_id();
+    const int e = blockIdx.x * kWaves + w;
+    if (e >= count) return;
+    const int n = d.n;
+    uint8_t* pw = sp[w];
+    for (int j = l; j < NP; j += kWave) pw[j] = j < n ? perms[(size_t)e * n + j] : 0;
+    wave_sync();
+    long long* dout = deltas ? deltas + (size_t)e * n * n : nullptr;
+    long long goal, key;
+    goal_delta_mfma<NP, SYM>(n, sF, sD, sFT, sDT, pw, sri[w], dout != nullptr, dout, goal, key);
+    if (dout)
+        for (int j = l; j < n; j += kWave) dout[(size_t)j * n + j] = 0;
+    if (l == 0) goals[e] = goal;
+}
+
+// ------------------------------------------------------------------ launchers
+template <bool SYM>
+static hipError_t fused_launch_np(const InstDesc& d, hipStream_t st)
+{
+    const dim3 grid((unsigned)((d.P + kWaves - 1) / kWaves)), block(kWaves * kWave);
+    switch (d.npad) {
+    case 32: hipLaunchKernelGGL((k_fused_step<32, SYM>), grid, block, 0, st, d); break;
+    case 64: hipLaunchKernelGGL((k_fused_step<64, SYM>), grid, block, 0, st, d); break;
+    case 96: hipLaunchKernelGGL((k_fused_step<96, SYM>), grid, block, 0, st, d); break;
+    case 128: hipLaunchKernelGGL((k_fused_step<128, SYM>), grid, block, 0, st, d); break;
+    case 160: hipLaunchKernelGGL((k_fused_step<160, SYM>), grid, block, 0, st, d); break;
+    default: return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160; }
+
+hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipEvent_t* ev)
+{
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
+    e = d.sym ? fused_launch_np<true>(d, st) : fused_launch_np<false>(d, st);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[7], st)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[8], st)) != hipSuccess) return e;
+    e = launch_bests(d, 0, order, st);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[9], st)) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <bool SYM>
+static hipError_t eval_launch_np(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
+                                 long long* deltas, hipStream_t st)
+{
+    const dim3 grid((unsigned)((count + kWaves - 1) / kWaves)), block(kWaves * kWave);
+    switch (d.npad) {
+    case 32: hipLaunchKernelGGL((k_eval_mfma<32, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 64: hipLaunchKernelGGL((k_eval_mfma<64, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 96: hipLaunchKernelGGL((k_eval_mfma<96, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 128: hipLaunchKernelGGL((k_eval_mfma<128, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 160: hipLaunchKernelGGL((k_eval_mfma<160, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    default: return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals, long long* deltas,
+                            hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    return d.sym ? eval_launch_np<true>(d, perms, count, goals, deltas, st)
+                 : eval_launch_np<false>(d, perms, count, goals, deltas, st);
 }
 
 }  // namespace qap

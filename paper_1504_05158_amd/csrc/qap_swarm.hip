@@ -263,10 +263,10 @@ int enqueue_iteration(qap_swarm* h)
             ev = prof_events(h);
             if (!ev) return dev_err(h, hipErrorOutOfMemory);
         }
-        if (h->engine == QAP_ENGINE_PLAIN)
-            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream, ev);
-        else
+        if (h->engine == QAP_ENGINE_FUSED && qap::fused_supported(I.d))
             e = qap::launch_fused_step(I.d, I.order, h->stream, ev);
+        else  // per-stage kernels: the plain engine, and the int32 range fallback of the fused one
+            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream, ev);
         if (e != hipSuccess) return dev_err(h, e);
     }
     if (h->profiling) h->prof_iters += 1;
@@ -323,7 +323,6 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
         if (prms[k].engine != prms[0].engine) return QAP_ERR_INVALID_ARG;
         rc = choose_path(&insts[k], &prms[k], prms[0].engine, &path[(size_t)k], &sym[(size_t)k], &mul24[(size_t)k]);
         if (rc != QAP_OK) return rc;
-        if (prms[k].engine == QAP_ENGINE_FUSED) return QAP_ERR_UNSUPPORTED;
     }
     qap_swarm* h = new (std::nothrow) qap_swarm();
     if (!h) return QAP_ERR_NOMEM;
@@ -516,7 +515,7 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
     if (e == hipSuccess && deltas) e = hipMalloc(&dd, sizeof(long long) * (size_t)count * n * n);
     if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
-        if (I->d.path == 1)
+        if (I->d.path == 1 && qap::fused_supported(I->d))
             e = qap::launch_eval_mfma(I->d, dp, count, dg, dd, h->stream);
         else
             e = qap::launch_goal_delta_i32(I->d, I->mul24, h->grid_gd, dp, count, 1, dg, dd, h->stream);

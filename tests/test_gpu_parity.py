@@ -15,7 +15,7 @@ from _parity import assert_states_equal, assert_v_close, make_gpu, oracle_from_s
 
 pytestmark = pytest.mark.gpu
 
-ENGINES = ["plain"]
+ENGINES = ["fused", "plain"]
 
 
 @pytest.fixture(scope="module")
