@@ -18,7 +18,10 @@ def sources() -> list[str]:
 
 def build(verbose: bool = False) -> str:
     objs = []
-    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+    # -ffp-contract=off: no multiply-add fusion, so every binary32 value (the
+    # SecondTarget keys above all) is computed with the roundings the source
+    # states, identically wherever it is recomputed
+    flags = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
     bdir = os.path.join(HERE, "_build")

@@ -45,7 +45,12 @@ struct InstDesc {
     const int8_t* FT8;      // [npad][npad] : F^T
     const int8_t* DT8;      // [npad][npad] : D^T
     // particle state; index [k] by particle, two buffers selected by iteration parity
-    float* V[2];            // [P][n][n] row = location, column = facility
+    // V is kept column-scaled: V[r][c] = fl(U[r][c] * Vinv[c]) with U the
+    // unnormalised S_v output and Vinv the reciprocal column norm (1 for raw
+    // S_v).  Applying the scale on read gives the same binary32 value as
+    // storing the normalised matrix, and lets the velocity pass stream.
+    float* V[2];            // [P][n][n] U, row = location, column = facility
+    float* Vinv[2];         // [P][n]    column scale
     uint8_t* X[2];          // [P][n]   p[i] = location of facility i
     uint8_t* PL;            // [P][n]
     long long* goal;        // [P]

@@ -3,9 +3,10 @@
 // gfx950 int8 MFMA (v_mfma_i32_32x32x32_i8, int32 accumulation).
 //
 // Per particle (wave):
-//  A. stream V(t) once, lane = column (facility), 64 columns per pass, the
-//     column held in registers: the velocity update of eq. (velocity) with S_v,
-//     the column norm, the store of V(t+1) (the other buffer), and the
+//  A. stream V(t) once, lane = column (facility), 64 columns per pass (each
+//     load a 256-byte row segment): the velocity update of eq. (velocity) with
+//     the S_v clamp, the column norm (stored as a column scale applied on the
+//     next read), the store of V(t+1) into the other buffer, and the
 //     SecondTarget column caches (max key, Z-cell key).  The at most three
 //     cells per column touched by the attraction terms (rows of X, P^L, P^G)
 //     are corrected after the pass.
@@ -149,6 +150,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     BT = mfma32(dpt[a][kc], gb, BT);
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
             if (y >= n) continue;
             const RowInfo cy = sri[y];
 #pragma unroll
@@ -177,6 +179,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 const long long key = ((long long)del << 16) | (x << 8) | y;
                 bestkey = key < bestkey ? key : bestkey;
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     // wave minimum
@@ -238,6 +241,8 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     const float c1 = d.c1, vmax = d.vmax;
 
     // ---- A. velocity stream + SecondTarget caches
+    const float* Sp = d.Vinv[cur] + (size_t)k * n;
+    float* Sq = d.Vinv[cur ^ 1] + (size_t)k * n;
     StState<CPL> st;
     st.rowbits = 0;
 #pragma unroll
@@ -248,54 +253,45 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
         const int c = l + kWave * kk;
         const bool on = c < n;
         int xr = 0, lr = 0, gr = 0;
-        float vx = 0.0f, vl = 0.0f, vg = 0.0f;
+        float sc = 1.0f, vx = 0.0f, vl = 0.0f, vg = 0.0f;
         if (on) {
             xr = Xk[c];
             lr = d.PL[(size_t)k * n + c];
             gr = d.PG[(size_t)g * n + c];
-            vx = Vp[(size_t)xr * n + c];
-            vl = Vp[(size_t)lr * n + c];
-            vg = Vp[(size_t)gr * n + c];
+            sc = Sp[c];
+            vx = __fmul_rn(Vp[(size_t)xr * n + c], sc);
+            vl = __fmul_rn(Vp[(size_t)lr * n + c], sc);
+            vg = __fmul_rn(Vp[(size_t)gr * n + c], sc);
         }
-        float col[NP];
-#pragma unroll
-        for (int r = 0; r < NP; ++r) col[r] = (on && r < n) ? Vp[(size_t)r * n + c] : 0.0f;
         float m = -INFINITY, sum = 0.0f;
-#pragma unroll
-        for (int r = 0; r < NP; ++r) {
-            if (r < n) {
-                m = fmaxf(m, col[r]);
-                const float t = clampv(__fmul_rn(c1, col[r]), vmax);
-                col[r] = t;
-                sum = __fadd_rn(sum, fabsf(t));
-            }
-        }
-        // the (at most three) cells with attraction terms
-        float tx, tl = 0.0f, tg = 0.0f;
-        {
-            const float ax = (float)((xr == lr) - 1), bx = (float)((xr == gr) - 1);
-            tx = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vx), __fmul_rn(s2, ax)), __fmul_rn(s3, bx)), vmax);
-            sum = __fadd_rn(sum, fabsf(tx) - fabsf(clampv(__fmul_rn(c1, vx), vmax)));
-        }
-        const bool dl = lr != xr, dg = gr != xr && gr != lr;
-        if (dl) {
-            const float bl = (float)(lr == gr);
-            tl = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vl), s2), __fmul_rn(s3, bl)), vmax);
-            sum = __fadd_rn(sum, fabsf(tl) - fabsf(clampv(__fmul_rn(c1, vl), vmax)));
-        }
-        if (dg) {
-            tg = clampv(__fadd_rn(__fmul_rn(c1, vg), s3), vmax);
-            sum = __fadd_rn(sum, fabsf(tg) - fabsf(clampv(__fmul_rn(c1, vg), vmax)));
-        }
-        const float inv = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
         if (on) {
-#pragma unroll
-            for (int r = 0; r < NP; ++r)
-                if (r < n) Vq[(size_t)r * n + c] = d.norm ? __fmul_rn(col[r], inv) : col[r];
-            // same lane, same address, later in program order: these stores win
-            Vq[(size_t)xr * n + c] = d.norm ? __fmul_rn(tx, inv) : tx;
-            if (dl) Vq[(size_t)lr * n + c] = d.norm ? __fmul_rn(tl, inv) : tl;
-            if (dg) Vq[(size_t)gr * n + c] = d.norm ? __fmul_rn(tg, inv) : tg;
+            // one coalesced row segment per load; S_v's clamp applied, scale deferred
+#pragma unroll 16
+            for (int r = 0; r < n; ++r) {
+                const float v = __fmul_rn(Vp[(size_t)r * n + c], sc);
+                m = fmaxf(m, v);
+                const float t = clampv(__fmul_rn(c1, v), vmax);
+                sum = __fadd_rn(sum, fabsf(t));
+                Vq[(size_t)r * n + c] = t;
+            }
+            // the (at most three) cells with attraction terms, stored after the
+            // plain value of the same cell by the same lane (program order)
+            const float ax = (float)((xr == lr) - 1), bx = (float)((xr == gr) - 1);
+            const float tx = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vx), __fmul_rn(s2, ax)), __fmul_rn(s3, bx)), vmax);
+            sum = __fadd_rn(sum, fabsf(tx) - fabsf(clampv(__fmul_rn(c1, vx), vmax)));
+            Vq[(size_t)xr * n + c] = tx;
+            if (lr != xr) {
+                const float bl = (float)(lr == gr);
+                const float tl = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vl), s2), __fmul_rn(s3, bl)), vmax);
+                sum = __fadd_rn(sum, fabsf(tl) - fabsf(clampv(__fmul_rn(c1, vl), vmax)));
+                Vq[(size_t)lr * n + c] = tl;
+            }
+            if (gr != xr && gr != lr) {
+                const float tg = clampv(__fadd_rn(__fmul_rn(c1, vg), s3), vmax);
+                sum = __fadd_rn(sum, fabsf(tg) - fabsf(clampv(__fmul_rn(c1, vg), vmax)));
+                Vq[(size_t)gr * n + c] = tg;
+            }
+            Sq[c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
         }
         st.cal[kk] = on;
         st.zal[kk] = on;
@@ -310,7 +306,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     // ---- B. SecondTarget
     uint8_t* pw = sp[w];
     for (int j = n + l; j < NP; j += kWave) pw[j] = 0;
-    st_select<CPL>(n, d.depth, Vp, st, pw, d.seed, tau, s, g);
+    st_select<CPL>(n, d.depth, Vp, Sp, st, pw, d.seed, tau, s, g);
     wave_sync();
 
     // ---- C. goal, pair-exchange deltas, one exchange

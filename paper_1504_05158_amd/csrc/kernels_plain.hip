@@ -45,15 +45,13 @@ __global__ void k_init_vel(InstDesc d)
         V[(size_t)r * n + c] = t;
         sum = __fadd_rn(sum, fabsf(t));
     }
-    if (d.norm && sum > 0.0f) {
-        const float inv = 1.0f / sum;
-        for (int r = 0; r < n; ++r) V[(size_t)r * n + c] = __fmul_rn(V[(size_t)r * n + c], inv);
-    }
+    d.Vinv[0][(size_t)k * n + c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
 }
 
 // ------------------------------------------------------------------ velocity
 // eq. (velocity): V(t+1) = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X)) at
-// state t, one thread per (particle, column); two passes for the column norm.
+// state t, one thread per (particle, column), one pass: the unnormalised
+// values and the column scale are stored.
 __global__ void k_velocity(InstDesc d)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,27 +69,19 @@ __global__ void k_velocity(InstDesc d)
     const int pl = d.PL[(size_t)k * n + c];
     const int pg = d.PG[(size_t)g * n + c];
     const float* Vc = d.V[cur] + (size_t)k * n * n;
+    const float sc = d.Vinv[cur][(size_t)k * n + c];
     float* Vn = d.V[cur ^ 1] + (size_t)k * n * n;
     float sum = 0.0f;
     for (int r = 0; r < n; ++r) {
         const float a = (float)((r == pl) - (r == x)), b = (float)((r == pg) - (r == x));
-        float t = __fmul_rn(d.c1, Vc[(size_t)r * n + c]);
+        float t = __fmul_rn(d.c1, __fmul_rn(Vc[(size_t)r * n + c], sc));
         t = __fadd_rn(t, __fmul_rn(s2, a));
         t = __fadd_rn(t, __fmul_rn(s3, b));
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
-        if (d.norm) sum = __fadd_rn(sum, fabsf(t));
-        else Vn[(size_t)r * n + c] = t;
+        sum = __fadd_rn(sum, fabsf(t));
+        Vn[(size_t)r * n + c] = t;
     }
-    if (!d.norm) return;
-    const float inv = sum > 0.0f ? 1.0f / sum : 1.0f;
-    for (int r = 0; r < n; ++r) {
-        const float a = (float)((r == pl) - (r == x)), b = (float)((r == pg) - (r == x));
-        float t = __fmul_rn(d.c1, Vc[(size_t)r * n + c]);
-        t = __fadd_rn(t, __fmul_rn(s2, a));
-        t = __fadd_rn(t, __fmul_rn(s3, b));
-        t = fminf(fmaxf(t, -d.vmax), d.vmax);
-        Vn[(size_t)r * n + c] = __fmul_rn(t, inv);
-    }
+    d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
 }
 
 // ------------------------------------------------------------------ S_x
@@ -106,9 +96,10 @@ __global__ __launch_bounds__(256) void k_second_target(InstDesc d)
     const int cur = tprev & 1;
     const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
     const float* V = d.V[cur] + (size_t)k * n * n;
+    const float* Vs = d.Vinv[cur] + (size_t)k * n;
     StState<CPL> st;
-    st_init_scan<CPL>(n, V, d.X[cur] + (size_t)k * n, st);
-    st_select<CPL>(n, d.depth, V, st, d.Xnew + (size_t)k * n, d.seed, (uint32_t)tprev + 1u, s, g);
+    st_init_scan<CPL>(n, V, Vs, d.X[cur] + (size_t)k * n, st);
+    st_select<CPL>(n, d.depth, V, Vs, st, d.Xnew + (size_t)k * n, d.seed, (uint32_t)tprev + 1u, s, g);
 }
 
 template __global__ void k_second_target<1>(InstDesc);

@@ -186,6 +186,8 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     }
     TRY(dalloc(I, &d.V[0], P * nn));
     TRY(dalloc(I, &d.V[1], P * nn));
+    TRY(dalloc(I, &d.Vinv[0], P * n));
+    TRY(dalloc(I, &d.Vinv[1], P * n));
     TRY(dalloc(I, &d.X[0], P * n));
     TRY(dalloc(I, &d.X[1], P * n));
     TRY(dalloc(I, &d.PL, P * n));
@@ -417,7 +419,19 @@ int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st)
             for (size_t i = 0; i < rows * n; ++i) dst[i] = buf[i];
         return ee;
     };
-    if (e == hipSuccess && st->V) e = hipMemcpy(st->V, d.V[cur], P * n * n * sizeof(float), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && st->V) {
+        // V = fl(U * scale) per column, the value every kernel reads
+        std::vector<float> sc(P * n);
+        e = hipMemcpy(st->V, d.V[cur], P * n * n * sizeof(float), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(sc.data(), d.Vinv[cur], P * n * sizeof(float), hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (size_t k = 0; k < P; ++k)
+                for (size_t r = 0; r < n; ++r)
+                    for (size_t c = 0; c < n; ++c) {
+                        volatile float prod = st->V[(k * n + r) * n + c] * sc[k * n + c];
+                        st->V[(k * n + r) * n + c] = prod;
+                    }
+    }
     if (e == hipSuccess && st->X) e = perms_out(d.X[cur], P, st->X);
     if (e == hipSuccess && st->PL) e = perms_out(d.PL, P, st->PL);
     if (e == hipSuccess && st->goal) e = hipMemcpy(st->goal, d.goal, P * 8, hipMemcpyDeviceToHost);
@@ -469,6 +483,10 @@ int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
         return hipMemcpy(dst, buf.data(), rows * n, hipMemcpyHostToDevice);
     };
     if (e == hipSuccess) e = hipMemcpy(d.V[cur], st->V, P * n * n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const std::vector<float> ones(P * n, 1.0f);
+        e = hipMemcpy(d.Vinv[cur], ones.data(), P * n * sizeof(float), hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess) e = perms_in(st->X, P, d.X[cur]);
     if (e == hipSuccess) e = perms_in(st->PL, P, d.PL);
     if (e == hipSuccess) e = hipMemcpy(d.goal, st->goal, P * 8, hipMemcpyHostToDevice);

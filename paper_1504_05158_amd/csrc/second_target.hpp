@@ -1,7 +1,8 @@
 // S_x = SecondTarget (Alg. 1 of the paper) for one particle on one wave64.
 //
-// Input: the particle's V(t) (global, [n][n], row = location, column =
-// facility) and its solution z = X(t).  Keys are W = X + V in binary32: a cell
+// Input: the particle's V(t) (global, [n][n] unnormalised U with the
+// per-column scale Vs, V = fl(U * Vs); row = location, column = facility) and
+// its solution z = X(t).  Keys are W = X + V in binary32: a cell
 // of Z has key 1 + v, every other cell v.  Selection i = 0 .. n-1 takes the
 // maximum key over the remaining rows and columns, leaving out the cells of
 // Z while i < depth; exact ties are broken by the k-th tied cell in
@@ -37,10 +38,11 @@ struct StState {
 
 // Exact best non-Z key of column c over the alive rows (whole wave).
 template <int CPL>
-__device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, int c, int zr, unsigned rowbits,
-                                          float& mv, int& mr, int& mc)
+__device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, const float* __restrict__ Vs, int c,
+                                          int zr, unsigned rowbits, float& mv, int& mr, int& mc)
 {
     const int l = lane_id();
+    const float sc = Vs[c];
     float v[CPL];
     bool ok[CPL];
     float best = -INFINITY;
@@ -48,7 +50,7 @@ __device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, in
     for (int j = 0; j < CPL; ++j) {
         const int r = l + kWave * j;
         ok[j] = (r < n) && ((rowbits >> j) & 1u) && (r != zr);
-        v[j] = ok[j] ? V[(size_t)r * n + c] : -INFINITY;
+        v[j] = ok[j] ? __fmul_rn(V[(size_t)r * n + c], sc) : -INFINITY;
         best = fmaxf(best, v[j]);
     }
     const float m = wave_max(best);
@@ -66,17 +68,18 @@ __device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, in
 
 // Row of the k-th tied cell (ascending row) of column c with key m.
 template <int CPL>
-__device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ V, int c, int zr, bool withZ,
-                                               unsigned rowbits, float m, int k)
+__device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ V, const float* __restrict__ Vs,
+                                               int c, int zr, bool withZ, unsigned rowbits, float m, int k)
 {
     const int l = lane_id();
+    const float sc = Vs[c];
 #pragma unroll
     for (int j = 0; j < CPL; ++j) {
         const int r = l + kWave * j;
         bool ok = (r < n) && ((rowbits >> j) & 1u) && (withZ || r != zr);
         float key = -INFINITY;
         if (ok) {
-            const float v = V[(size_t)r * n + c];
+            const float v = __fmul_rn(V[(size_t)r * n + c], sc);
             key = (r == zr) ? 1.0f + v : v;
         }
         const uint64_t b = ballot64(ok && key == m);
@@ -94,8 +97,8 @@ __device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ 
 
 // Initial per-column cache by a full scan of V (exact, not stale).
 template <int CPL>
-__device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V, const uint8_t* __restrict__ z,
-                                             StState<CPL>& s)
+__device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V, const float* __restrict__ Vs,
+                                             const uint8_t* __restrict__ z, StState<CPL>& s)
 {
     const int l = lane_id();
     s.rowbits = 0;
@@ -114,12 +117,15 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
         s.nzc[k] = 0;
         s.stale[k] = false;
     }
+    float sc[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) sc[k] = (l + kWave * k < n) ? Vs[l + kWave * k] : 1.0f;
     for (int r = 0; r < n; ++r) {
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
             const int c = l + kWave * k;
             if (c < n) {
-                const float v = V[(size_t)r * n + c];
+                const float v = __fmul_rn(V[(size_t)r * n + c], sc[k]);
                 if (r == s.zr[k]) {
                     s.zk[k] = 1.0f + v;
                 } else if (v > s.nzv[k]) {
@@ -134,7 +140,8 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
 
 // Run the n selections.  Writes out[c] = chosen row for every column c < n.
 template <int CPL>
-__device__ void st_select(int n, int depth, const float* __restrict__ V, StState<CPL>& s, uint8_t* out,
+__device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
+                          StState<CPL>& s, uint8_t* out,
                           uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm)
 {
     const int l = lane_id();
@@ -151,7 +158,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, StState
                 const int c = owner + kWave * k;
                 const int zr = readlane_i32(s.zr[k], owner);
                 float mv; int mr, mc;
-                st_rescan<CPL>(n, V, c, zr, s.rowbits, mv, mr, mc);
+                st_rescan<CPL>(n, V, Vs, c, zr, s.rowbits, mv, mr, mc);
                 if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
             }
         }
@@ -214,7 +221,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, StState
                     const int zr = readlane_i32(s.zr[k], owner);
                     const bool withZ = !skipZ && readlane_i32((int)s.zal[k], owner);
                     selc = c;
-                    selr = st_kth_tied_row<CPL>(n, V, c, zr, withZ, s.rowbits, m, kk - before);
+                    selr = st_kth_tied_row<CPL>(n, V, Vs, c, zr, withZ, s.rowbits, m, kk - before);
                 } else {
                     kk -= tot;
                 }

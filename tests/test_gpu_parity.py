@@ -179,3 +179,48 @@ def test_determinism_and_checkpoint(q, engine):
         assert np.array_equal(np.asarray(sa[k]), np.asarray(sc[k])), k
     a.close()
     c.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n,depth", [(5, 0), (17, 2), (70, 2), (128, 0), (128, 2), (150, 3)])
+def test_secondtarget_with_exact_ties(q, orc, engine, n, depth):
+    """Quantised velocities make exact key ties frequent; X(t+1) (local search
+    off) must equal the oracle's SecondTarget, tie-breaks included."""
+    rng = np.random.default_rng(n * 10 + depth)
+    F, D = gen.uniform_instance(n, 0, 20, n)
+    m, S = 2, 16
+    cfg = run_cfg(num_swarms=m, particles_per_swarm=S, norm=False, depth=depth, local_search=False, seed=3)
+    announce("ties", engine, n, depth)
+    sw = make_gpu(q, F, D, dict(cfg, engine=engine))
+    st = sw.get_state()
+    V = (rng.integers(-3, 4, size=(m * S, n, n)) / 4.0).astype(np.float32)
+    st["V"] = V
+    sw.set_state(st)
+    sw.step(1)
+    g = sw.get_state()
+    nties = 0
+    for k in range(m * S):
+        W = orc.keys(V[k].astype(np.float64), st["X"][k])
+        ref, ties = orc.second_target(W, st["X"][k], depth, seed=3, t=st["t"] + 1, particle=k % S, swarm=k // S,
+                                      return_ties=True)
+        nties += int((ties > 1).sum())
+        assert np.array_equal(g["X"][k], ref), (n, depth, k)
+    assert nties > 0
+    sw.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+def test_norm_run_with_column_scales_n128(q, orc, engine):
+    """Norm runs keep V as a matrix times per-column scales; near-equal keys
+    1 + v arise often at n = 128.  Ten re-synchronised one-step comparisons."""
+    F, D = gen.uniform_instance(128, 0, 127, 168)
+    cfg = run_cfg(num_swarms=2, particles_per_swarm=8, norm=True, depth=2, local_search=True, seed=135)
+    announce("normscale", engine)
+    sw = make_gpu(q, F, D, dict(cfg, engine=engine))
+    for it in range(10):
+        st = sw.get_state()
+        o = oracle_from_state(orc, F, D, cfg, st)
+        o.step()
+        sw.step(1)
+        assert_states_equal(sw.get_state(), o.state(), what="iteration %d" % (it + 1))
+    sw.close()
