@@ -208,6 +208,45 @@ __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF,
 
 __device__ __forceinline__ float clampv(float t, float vmax) { return fminf(fmaxf(t, -vmax), vmax); }
 
+// One column of the velocity pass: row r of the column is vp[r*n] (the
+// lane's column of V(t)); writes the clamped c1*v to vq[r*n]; returns the sum
+// of |.| and the column's largest value m1 (first row r1) and runner-up m2.
+// Rows are loaded in batches so that many loads are in flight.
+__device__ __forceinline__ float stream_column(const float* __restrict__ vp, float* __restrict__ vq, int n, float sc,
+                                               float c1, float vmax, float& m1, int& r1, float& m2)
+{
+    constexpr int B = 16;
+    float sum = 0.0f;
+    int r0 = 0;
+    for (; r0 + B <= n; r0 += B) {
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = vp[(size_t)(r0 + u) * n];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const float x = __fmul_rn(v[u], sc);
+            const bool gt = x > m1;
+            m2 = gt ? m1 : fmaxf(m2, x);
+            r1 = gt ? r0 + u : r1;
+            m1 = gt ? x : m1;
+            const float t = clampv(__fmul_rn(c1, x), vmax);
+            sum = __fadd_rn(sum, fabsf(t));
+            vq[(size_t)(r0 + u) * n] = t;
+        }
+    }
+    for (int r = r0; r < n; ++r) {
+        const float x = __fmul_rn(vp[(size_t)r * n], sc);
+        const bool gt = x > m1;
+        m2 = gt ? m1 : fmaxf(m2, x);
+        r1 = gt ? r : r1;
+        m1 = gt ? x : m1;
+        const float t = clampv(__fmul_rn(c1, x), vmax);
+        sum = __fadd_rn(sum, fabsf(t));
+        vq[(size_t)r * n] = t;
+    }
+    return sum;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ fused step
@@ -263,17 +302,10 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
             vl = __fmul_rn(Vp[(size_t)lr * n + c], sc);
             vg = __fmul_rn(Vp[(size_t)gr * n + c], sc);
         }
-        float m = -INFINITY, sum = 0.0f;
+        float m1 = -INFINITY, m2 = -INFINITY, sum = 0.0f;
+        int r1 = -1;
         if (on) {
-            // one coalesced row segment per load; S_v's clamp applied, scale deferred
-#pragma unroll 16
-            for (int r = 0; r < n; ++r) {
-                const float v = __fmul_rn(Vp[(size_t)r * n + c], sc);
-                m = fmaxf(m, v);
-                const float t = clampv(__fmul_rn(c1, v), vmax);
-                sum = __fadd_rn(sum, fabsf(t));
-                Vq[(size_t)r * n + c] = t;
-            }
+            sum = stream_column(Vp + c, Vq + c, n, sc, c1, vmax, m1, r1, m2);
             // the (at most three) cells with attraction terms, stored after the
             // plain value of the same cell by the same lane (program order)
             const float ax = (float)((xr == lr) - 1), bx = (float)((xr == gr) - 1);
@@ -293,14 +325,19 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
             }
             Sq[c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
         }
+        // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
+        // when the column maximum is unique and off the Z row; the runner-up
+        // value bounds it when the maximum sits on the Z row
+        if (on && r1 != xr && m2 < m1) {
+            st.nzv[kk] = m1; st.nzr[kk] = r1; st.nzc[kk] = 1; st.stale[kk] = false;
+        } else {
+            st.nzv[kk] = on ? (r1 == xr ? m2 : m1) : -INFINITY;
+            st.nzr[kk] = -1; st.nzc[kk] = 0; st.stale[kk] = on;
+        }
         st.cal[kk] = on;
         st.zal[kk] = on;
         st.zr[kk] = on ? xr : -1;
         st.zk[kk] = on ? 1.0f + vx : -INFINITY;
-        st.nzv[kk] = on ? m : -INFINITY;  // upper bound of the non-Z keys
-        st.nzr[kk] = -1;
-        st.nzc[kk] = 0;
-        st.stale[kk] = on;
     }
 
     // ---- B. SecondTarget

@@ -12,11 +12,9 @@
 // it keeps the Z cell's key and a cache of the best non-Z key over the alive
 // rows (value, first row, count).  The cache is an upper bound once one of
 // its rows may have gone ("stale"); it is recomputed by the whole wave
-// (one coalesced-by-lane column read) only when a selection actually needs
-// the exact value: always before depth, and afterwards only when the Z cell
-// is gone or does not beat the bound.  A selection is then one wave max plus
-// a ballot, O(n) per particle-iteration instead of the O(n^2) rescans of the
-// plain procedure.
+// (one read of the column) only when the column's bound reaches the current
+// maximum.  A selection is then one wave max plus a ballot, O(n) per
+// particle-iteration instead of the O(n^3) scans of the plain procedure.
 #pragma once
 #include "common.hpp"
 #include "philox.hpp"
@@ -139,48 +137,59 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
 }
 
 // Run the n selections.  Writes out[c] = chosen row for every column c < n.
+// A column's candidate is exact unless its cache is stale; a stale cache only
+// bounds the true value from above, so the maximum over all candidates is
+// the true maximum as soon as every column that reaches it is exact.  Only
+// those columns are rescanned (lazy argmax), and the loop repeats until the
+// columns at the maximum are all exact.
 template <int CPL>
 __device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
-                          StState<CPL>& s, uint8_t* out,
-                          uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm)
+                          StState<CPL>& s, uint8_t* out, uint64_t seed, uint32_t iter, uint32_t member,
+                          uint32_t swarm)
 {
     const int l = lane_id();
     for (int i = 0; i < n; ++i) {
         const bool skipZ = i < depth;
-        // 1. exact caches where this selection needs them
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            const bool need = s.cal[k] && s.stale[k] && (skipZ || !s.zal[k] || !(s.zk[k] > s.nzv[k]));
-            uint64_t b = ballot64(need);
-            while (b) {
-                const int owner = __ffsll((long long)b) - 1;
-                b &= b - 1;
-                const int c = owner + kWave * k;
-                const int zr = readlane_i32(s.zr[k], owner);
-                float mv; int mr, mc;
-                st_rescan<CPL>(n, V, Vs, c, zr, s.rowbits, mv, mr, mc);
-                if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
-            }
-        }
-        // 2. per-column candidate (value, count, first row)
-        float cv[CPL];
+        float cv[CPL], m;
         int cc[CPL], cr[CPL];
-        float lbest = -INFINITY;
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            float v = s.nzv[k];
-            int cnt = s.nzc[k], row = s.nzr[k];
-            if (!skipZ && s.zal[k]) {
-                if (s.zk[k] > s.nzv[k]) { v = s.zk[k]; cnt = 1; row = s.zr[k]; }
-                else if (s.zk[k] == s.nzv[k]) { cnt += 1; row = min(row, s.zr[k]); }
-            }
-            if (!s.cal[k] || cnt == 0) v = -INFINITY;
-            cv[k] = v; cc[k] = cnt; cr[k] = row;
-            lbest = fmaxf(lbest, v);
-        }
-        const float m = wave_max(lbest);
-        // 3. tied columns
         uint64_t bal[CPL];
+        for (;;) {
+            // per-column candidate (value, count, first row); `inexact` if the
+            // value is only an upper bound
+            bool inexact[CPL];
+            float lbest = -INFINITY;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                float v = s.nzv[k];
+                int cnt = s.nzc[k], row = s.nzr[k];
+                bool inx = s.stale[k];
+                if (!skipZ && s.zal[k]) {
+                    if (s.zk[k] > s.nzv[k]) { v = s.zk[k]; cnt = 1; row = s.zr[k]; inx = false; }
+                    else if (s.zk[k] == s.nzv[k]) { cnt += 1; row = min(row, s.zr[k]); }
+                }
+                if (!s.cal[k] || (!inx && cnt == 0)) { v = -INFINITY; inx = false; }
+                cv[k] = v; cc[k] = cnt; cr[k] = row; inexact[k] = inx;
+                lbest = fmaxf(lbest, v);
+            }
+            m = wave_max(lbest);
+            bool again = false;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k) {
+                uint64_t b = ballot64(inexact[k] && cv[k] == m);
+                again |= b != 0;
+                while (b) {
+                    const int owner = __ffsll((long long)b) - 1;
+                    b &= b - 1;
+                    const int c = owner + kWave * k;
+                    const int zr = readlane_i32(s.zr[k], owner);
+                    float mv; int mr, mc;
+                    st_rescan<CPL>(n, V, Vs, c, zr, s.rowbits, mv, mr, mc);
+                    if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
+                }
+            }
+            if (!again) break;
+        }
+        // columns at the maximum (all exact now)
         int ncols = 0;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
@@ -200,7 +209,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
                 }
         }
         if (selc < 0) {
-            // general tie: |M| cells, pick the k-th in column-major order
+            // |M| tied cells: take the k-th in column-major order
             int mycnt = 0;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) mycnt += ((bal[k] >> l) & 1ull) ? cc[k] : 0;
@@ -227,7 +236,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
                 }
             }
         }
-        // 4. apply the selection (a failed selection leaves the slot untouched)
+        // apply the selection (a failed selection leaves the slot untouched)
         if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
         if (l == (selc & 63)) out[selc] = (uint8_t)selr;
         if (l == (selr & 63)) s.rowbits &= ~(1u << (selr >> 6));
@@ -236,6 +245,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
             if (selc == l + kWave * k) s.cal[k] = false;
             if (s.cal[k]) {
                 if (s.zr[k] == selr) s.zal[k] = false;
+                // the cached row left, or the cached value was tied: bound only
                 if (!s.stale[k] && (s.nzr[k] == selr || s.nzc[k] > 1)) s.stale[k] = true;
             }
         }
