@@ -253,13 +253,14 @@ __device__ __forceinline__ float stream_column(const float* __restrict__ vp, flo
 template <int NP, bool SYM>
 __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 {
-    constexpr int CPL = (NP + kWave - 1) / kWave;
+    constexpr int CPL = NP <= 64 ? 1 : NP <= 128 ? 2 : 4;  // column slots per lane
     __shared__ __attribute__((aligned(16))) int8_t sF[NP * NP];
     __shared__ __attribute__((aligned(16))) int8_t sD[NP * NP];
     __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * NP];
     __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * NP];
     __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
     __shared__ RowInfo sri[kWaves][NP];
+    __shared__ StLds<CPL> slds[kWaves];
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
     __syncthreads();
 
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     // ---- B. SecondTarget
     uint8_t* pw = sp[w];
     for (int j = n + l; j < NP; j += kWave) pw[j] = 0;
-    st_select<CPL>(n, d.depth, Vp, Sp, st, pw, d.seed, tau, s, g);
+    st_select<CPL>(n, d.depth, Vp, Sp, st, pw, &slds[w], d.seed, tau, s, g);
     wave_sync();
 
     // ---- C. goal, pair-exchange deltas, one exchange

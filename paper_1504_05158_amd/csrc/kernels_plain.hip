@@ -88,6 +88,7 @@ __global__ void k_velocity(InstDesc d)
 template <int CPL>
 __global__ __launch_bounds__(256) void k_second_target(InstDesc d)
 {
+    __shared__ StLds<CPL> slds[4];
     const int wave = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
     if (wave >= d.P) return;
     const int k = wave;
@@ -99,12 +100,12 @@ __global__ __launch_bounds__(256) void k_second_target(InstDesc d)
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     StState<CPL> st;
     st_init_scan<CPL>(n, V, Vs, d.X[cur] + (size_t)k * n, st);
-    st_select<CPL>(n, d.depth, V, Vs, st, d.Xnew + (size_t)k * n, d.seed, (uint32_t)tprev + 1u, s, g);
+    st_select<CPL>(n, d.depth, V, Vs, st, d.Xnew + (size_t)k * n, &slds[threadIdx.x / kWave], d.seed,
+                   (uint32_t)tprev + 1u, s, g);
 }
 
 template __global__ void k_second_target<1>(InstDesc);
 template __global__ void k_second_target<2>(InstDesc);
-template __global__ void k_second_target<3>(InstDesc);
 template __global__ void k_second_target<4>(InstDesc);
 
 // ------------------------------------------------------------------ goal + deltas (int32)
@@ -458,7 +459,7 @@ hipError_t launch_init(const InstDesc& d, hipStream_t st)
 hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st,
                              hipEvent_t* ev)
 {
-    const int cpl = (d.n + kWave - 1) / kWave;
+    const int cpl = d.n <= 64 ? 1 : d.n <= 128 ? 2 : 4;
     const dim3 gst(blocks_for(d.P, 4)), bst(256);
     hipError_t e;
 #define REC(i) do { if (ev) { e = hipEventRecord(ev[i], st); if (e != hipSuccess) return e; } } while (0)
@@ -466,7 +467,6 @@ hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* ord
     switch (cpl) {
     case 1: hipLaunchKernelGGL(k_second_target<1>, gst, bst, 0, st, d); break;
     case 2: hipLaunchKernelGGL(k_second_target<2>, gst, bst, 0, st, d); break;
-    case 3: hipLaunchKernelGGL(k_second_target<3>, gst, bst, 0, st, d); break;
     default: hipLaunchKernelGGL(k_second_target<4>, gst, bst, 0, st, d); break;
     }
     e = hipGetLastError();

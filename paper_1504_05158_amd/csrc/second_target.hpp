@@ -18,6 +18,7 @@
 #pragma once
 #include "common.hpp"
 #include "philox.hpp"
+#include <climits>
 
 namespace qap {
 
@@ -136,119 +137,338 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
     }
 }
 
-// Run the n selections.  Writes out[c] = chosen row for every column c < n.
-// A column's candidate is exact unless its cache is stale; a stale cache only
-// bounds the true value from above, so the maximum over all candidates is
-// the true maximum as soon as every column that reaches it is exact.  Only
-// those columns are rescanned (lazy argmax), and the loop repeats until the
-// columns at the maximum are all exact.
+// Per-wave LDS scratch of the selection: the sorted Z cells, their compacted
+// alive subsequence, and dead-row / dead-column flags.
+template <int S>
+struct StLds {
+    int2 sorted[kWave * S];
+    int2 packed[kWave * S];
+    uint8_t deadrow[kMaxN];
+    uint8_t deadcol[kMaxN];
+};
+
+// Float -> int with the same order (signed compare); -0 is folded into +0 first.
+__device__ __forceinline__ int ordered_key(float f)
+{
+    int i = __float_as_int(f + 0.0f);
+    return i ^ ((i >> 31) & 0x7fffffff);
+}
+
+// One selection by the exact procedure: returns the column (uniform) and
+// sets selr.  A column's candidate is exact unless its cache is stale; a
+// stale cache only bounds the true value from above, so the maximum over all
+// candidates is the true maximum as soon as every column that reaches it is
+// exact.  Only those columns are rescanned (lazy argmax).
 template <int CPL>
-__device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
-                          StState<CPL>& s, uint8_t* out, uint64_t seed, uint32_t iter, uint32_t member,
-                          uint32_t swarm)
+__device__ int st_generic_pick(int n, int i, bool skipZ, const float* __restrict__ V, const float* __restrict__ Vs,
+                               StState<CPL>& s, uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm,
+                               int& selr)
 {
     const int l = lane_id();
-    for (int i = 0; i < n; ++i) {
-        const bool skipZ = i < depth;
-        float cv[CPL], m;
-        int cc[CPL], cr[CPL];
-        uint64_t bal[CPL];
-        for (;;) {
-            // per-column candidate (value, count, first row); `inexact` if the
-            // value is only an upper bound
-            bool inexact[CPL];
-            float lbest = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                float v = s.nzv[k];
-                int cnt = s.nzc[k], row = s.nzr[k];
-                bool inx = s.stale[k];
-                if (!skipZ && s.zal[k]) {
-                    if (s.zk[k] > s.nzv[k]) { v = s.zk[k]; cnt = 1; row = s.zr[k]; inx = false; }
-                    else if (s.zk[k] == s.nzv[k]) { cnt += 1; row = min(row, s.zr[k]); }
-                }
-                if (!s.cal[k] || (!inx && cnt == 0)) { v = -INFINITY; inx = false; }
-                cv[k] = v; cc[k] = cnt; cr[k] = row; inexact[k] = inx;
-                lbest = fmaxf(lbest, v);
-            }
-            m = wave_max(lbest);
-            bool again = false;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                uint64_t b = ballot64(inexact[k] && cv[k] == m);
-                again |= b != 0;
-                while (b) {
-                    const int owner = __ffsll((long long)b) - 1;
-                    b &= b - 1;
-                    const int c = owner + kWave * k;
-                    const int zr = readlane_i32(s.zr[k], owner);
-                    float mv; int mr, mc;
-                    st_rescan<CPL>(n, V, Vs, c, zr, s.rowbits, mv, mr, mc);
-                    if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
-                }
-            }
-            if (!again) break;
-        }
-        // columns at the maximum (all exact now)
-        int ncols = 0;
+    float cv[CPL], m;
+    int cc[CPL], cr[CPL];
+    uint64_t bal[CPL];
+    for (;;) {
+        bool inexact[CPL];
+        float lbest = -INFINITY;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            bal[k] = ballot64(cv[k] == m && cv[k] != -INFINITY);
-            ncols += __popcll(bal[k]);
+            float v = s.nzv[k];
+            int cnt = s.nzc[k], row = s.nzr[k];
+            bool inx = s.stale[k];
+            if (!skipZ && s.zal[k]) {
+                if (s.zk[k] > s.nzv[k]) { v = s.zk[k]; cnt = 1; row = s.zr[k]; inx = false; }
+                else if (s.zk[k] == s.nzv[k]) { cnt += 1; row = min(row, s.zr[k]); }
+            }
+            if (!s.cal[k] || (!inx && cnt == 0)) { v = -INFINITY; inx = false; }
+            cv[k] = v; cc[k] = cnt; cr[k] = row; inexact[k] = inx;
+            lbest = fmaxf(lbest, v);
         }
-        int selc = -1, selr = -1;
-        if (ncols == 1) {
+        m = wave_max(lbest);
+        bool again = false;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            uint64_t b = ballot64(inexact[k] && cv[k] == m);
+            again |= b != 0;
+            while (b) {
+                const int owner = __ffsll((long long)b) - 1;
+                b &= b - 1;
+                const int c = owner + kWave * k;
+                const int zr = readlane_i32(s.zr[k], owner);
+                float mv; int mr, mc;
+                st_rescan<CPL>(n, V, Vs, c, zr, s.rowbits, mv, mr, mc);
+                if (l == owner) { s.nzv[k] = mv; s.nzr[k] = mr; s.nzc[k] = mc; s.stale[k] = false; }
+            }
+        }
+        if (!again) break;
+    }
+    int ncols = 0;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        bal[k] = ballot64(cv[k] == m && cv[k] != -INFINITY);
+        ncols += __popcll(bal[k]);
+    }
+    int selc = -1;
+    selr = -1;
+    if (ncols == 1) {
+#pragma unroll
+        for (int k = 0; k < CPL; ++k)
+            if (bal[k]) {
+                const int owner = __ffsll((long long)bal[k]) - 1;
+                if (readlane_i32(cc[k], owner) == 1) {
+                    selc = owner + kWave * k;
+                    selr = readlane_i32(cr[k], owner);
+                }
+            }
+    }
+    if (selc < 0) {
+        // |M| tied cells: take the k-th in column-major order
+        int mycnt = 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) mycnt += ((bal[k] >> l) & 1ull) ? cc[k] : 0;
+        const int total = wave_sum_i32(mycnt);
+        const uint32_t w = stream_word(seed, 4u + (uint32_t)i, iter, member, swarm);
+        int kk = (int)bounded_u32(w, (uint32_t)total);
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            if (selc >= 0) break;
+            const int x = ((bal[k] >> l) & 1ull) ? cc[k] : 0;
+            const int incl = wave_incl_scan_i32(x);
+            const int tot = readlane_i32(incl, 63);
+            if (kk < tot) {
+                const uint64_t hit = ballot64(incl > kk && x > 0 && incl - x <= kk);
+                const int owner = __ffsll((long long)hit) - 1;
+                const int before = readlane_i32(incl - x, owner);
+                const int c = owner + kWave * k;
+                const int zr = readlane_i32(s.zr[k], owner);
+                const bool withZ = !skipZ && readlane_i32((int)s.zal[k], owner);
+                selc = c;
+                selr = st_kth_tied_row<CPL>(n, V, Vs, c, zr, withZ, s.rowbits, m, kk - before);
+            } else {
+                kk -= tot;
+            }
+        }
+    }
+    return selc;
+}
+
+// Per-lane bookkeeping of a selection (row selr, column selc).
+template <int CPL>
+__device__ __forceinline__ void st_apply(StState<CPL>& s, int selc, int selr)
+{
+    const int l = lane_id();
+    if (l == (selr & 63)) s.rowbits &= ~(1u << (selr >> 6));
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        if (selc == l + kWave * k) s.cal[k] = false;
+        if (s.cal[k]) {
+            if (s.zr[k] == selr) s.zal[k] = false;
+            // the cached row left, or the cached value was tied: bound only
+            if (!s.stale[k] && (s.nzr[k] == selr || s.nzc[k] > 1)) s.stale[k] = true;
+        }
+    }
+}
+
+// Bring the per-lane state up to date after selections recorded only in the
+// dead-row / dead-column flags.
+template <int CPL, class L>
+__device__ __forceinline__ void st_sync(int n, StState<CPL>& s, const L* lds)
+{
+    const int l = lane_id();
+    unsigned rb = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+        const int r = l + kWave * j;
+        if (r < n && !lds->deadrow[r]) rb |= 1u << j;
+    }
+    s.rowbits = rb;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int c = l + kWave * k;
+        if (s.cal[k] && lds->deadcol[c]) s.cal[k] = false;
+        if (s.cal[k]) {
+            if (s.zal[k] && lds->deadrow[s.zr[k]]) s.zal[k] = false;
+            if (!s.stale[k] && ((s.nzr[k] >= 0 && lds->deadrow[s.nzr[k]]) || s.nzc[k] > 1)) s.stale[k] = true;
+        }
+    }
+}
+
+// Largest non-Z bound over the alive columns (an upper bound of every non-Z key).
+template <int CPL>
+__device__ __forceinline__ float st_nonz_bound(const StState<CPL>& s)
+{
+    float b = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < CPL; ++k)
+        if (s.cal[k]) b = fmaxf(b, s.nzv[k]);
+    return wave_max(b);
+}
+
+// Run the n selections.  Writes out[c] = chosen row for every column c < n.
+// The first `depth` selections (Z cells excluded) use the exact procedure.
+// Afterwards the Z cells are sorted by key once; the best alive Z cell is
+// taken directly whenever its key beats both the next alive Z key and the
+// bound of all non-Z keys (then it is the unique maximum); otherwise the exact
+// procedure makes the selection.
+// Bitonic sort (descending by key, then ascending payload) of the 64*S
+// entries held as (key, payload) per slot and lane; writes them to LDS.  Kept
+// out of line: unrolled into the fused kernel it inflates register pressure.
+template <int S>
+__device__ __noinline__ void st_sort_desc(int2* sorted, int k0, int p0, int k1, int p1, int k2, int p2, int k3,
+                                          int p3)
+{
+    constexpr int NS = kWave * S;
+    const int l = lane_id();
+    int key[S], pay[S];
+    key[0] = k0; pay[0] = p0;
+    if constexpr (S > 1) { key[1] = k1; pay[1] = p1; }
+    if constexpr (S > 2) { key[2] = k2; pay[2] = p2; key[3] = k3; pay[3] = p3; }
+#pragma unroll
+    for (int size = 2; size <= NS; size <<= 1) {
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            int nk[S], np[S];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                int pk, pp;
+                if (stride < kWave) {
+                    pk = __shfl_xor(key[k], stride, kWave);
+                    pp = __shfl_xor(pay[k], stride, kWave);
+                } else {
+                    pk = key[k ^ (stride / kWave)];
+                    pp = pay[k ^ (stride / kWave)];
+                }
+                const int e = k * kWave + l;
+                const bool lower = (e & stride) == 0;
+                const bool desc = (e & size) == 0;
+                const bool self_first = key[k] > pk || (key[k] == pk && pay[k] < pp);
+                const bool keep = (lower == desc) ? self_first : !self_first;
+                nk[k] = keep ? key[k] : pk;
+                np[k] = keep ? pay[k] : pp;
+            }
+#pragma unroll
+            for (int k = 0; k < S; ++k) { key[k] = nk[k]; pay[k] = np[k]; }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) sorted[k * kWave + l] = make_int2(key[k], pay[k]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// Run the n selections.  Writes out[c] = chosen row for every column c < n.
+// The first `depth` selections (Z cells excluded) use the exact procedure.
+// Afterwards the Z cells are sorted by key once.  Taking a Z cell never
+// removes another Z cell (they share no row or column), and the bound on all
+// non-Z keys only falls, so from any state the selections that take the best
+// alive Z cell -- allowed while its key beats both the next alive Z key and
+// that bound, i.e. while it is the unique maximum -- form a run that is decided
+// at once: the alive sorted entries are compacted, each is compared with its
+// successor and the bound, and the longest acceptable prefix is taken.  The
+// selection after a run (a tie, or a non-Z cell that may win) uses the exact
+// procedure, then a new run starts.  lds: the wave's scratch.
+template <int CPL>
+__device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
+                          StState<CPL>& s, uint8_t* out, StLds<CPL>* lds, uint64_t seed, uint32_t iter,
+                          uint32_t member, uint32_t swarm)
+{
+    static_assert(CPL == 1 || CPL == 2 || CPL == 4, "column slots per lane must be 1, 2 or 4");
+    constexpr int NS = kWave * CPL;  // sort length, a power of two
+    const int l = lane_id();
+    for (int r = l; r < kMaxN; r += kWave) { lds->deadrow[r] = 0; lds->deadcol[r] = 0; }
+    wave_lds_sync();
+    int i = 0;
+    for (; i < depth && i < n; ++i) {
+        int selr;
+        const int selc = st_generic_pick<CPL>(n, i, true, V, Vs, s, seed, iter, member, swarm, selr);
+        if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
+        if (l == 0) { out[selc] = (uint8_t)selr; lds->deadcol[selc] = 1; lds->deadrow[selr] = 1; }
+        st_apply<CPL>(s, selc, selr);
+    }
+    if (i >= n) return;
+    // sorted Z cells (descending key), payload = column | Z row << 8
+    {
+        int kz[4] = {INT_MIN, INT_MIN, INT_MIN, INT_MIN}, pz[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            kz[k] = (s.cal[k] && s.zal[k]) ? ordered_key(s.zk[k]) : INT_MIN;
+            pz[k] = (l + kWave * k) | ((s.zr[k] & 0xff) << 8);
+        }
+        st_sort_desc<CPL>(lds->sorted, kz[0], pz[0], kz[1], pz[1], kz[2], pz[2], kz[3], pz[3]);
+    }
+    int ekey[CPL], epay[CPL];
+#pragma unroll
+    for (int k = 0; k < CPL; ++k) {
+        const int2 e = lds->sorted[k * kWave + l];
+        ekey[k] = e.x;
+        epay[k] = e.y;
+    }
+    const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    wave_lds_sync();
+    while (i < n) {
+        // ---- a run of Z cells taken at once
+        const int bound = ordered_key(st_nonz_bound<CPL>(s));
+        bool alive[CPL];
+        int rank[CPL], total = 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            alive[k] = ekey[k] != INT_MIN && !lds->deadcol[epay[k] & 0xff] && !lds->deadrow[epay[k] >> 8];
+            const uint64_t b = ballot64(alive[k]);
+            rank[k] = total + __popcll(b & below);
+            total += __popcll(b);
+        }
+        if (total > 0) {
 #pragma unroll
             for (int k = 0; k < CPL; ++k)
-                if (bal[k]) {
-                    const int owner = __ffsll((long long)bal[k]) - 1;
-                    if (readlane_i32(cc[k], owner) == 1) {
-                        selc = owner + kWave * k;
-                        selr = readlane_i32(cr[k], owner);
-                    }
-                }
-        }
-        if (selc < 0) {
-            // |M| tied cells: take the k-th in column-major order
-            int mycnt = 0;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) mycnt += ((bal[k] >> l) & 1ull) ? cc[k] : 0;
-            const int total = wave_sum_i32(mycnt);
-            const uint32_t w = stream_word(seed, 4u + (uint32_t)i, iter, member, swarm);
-            int kk = (int)bounded_u32(w, (uint32_t)total);
+                if (alive[k]) lds->packed[rank[k]] = make_int2(ekey[k], epay[k]);
+            wave_lds_sync();
+            int firstbad = INT_MAX;
 #pragma unroll
             for (int k = 0; k < CPL; ++k) {
-                if (selc >= 0) break;
-                const int x = ((bal[k] >> l) & 1ull) ? cc[k] : 0;
-                const int incl = wave_incl_scan_i32(x);
-                const int tot = readlane_i32(incl, 63);
-                if (kk < tot) {
-                    const uint64_t hit = ballot64(incl > kk && x > 0 && incl - x <= kk);
-                    const int owner = __ffsll((long long)hit) - 1;
-                    const int before = readlane_i32(incl - x, owner);
-                    const int c = owner + kWave * k;
-                    const int zr = readlane_i32(s.zr[k], owner);
-                    const bool withZ = !skipZ && readlane_i32((int)s.zal[k], owner);
-                    selc = c;
-                    selr = st_kth_tied_row<CPL>(n, V, Vs, c, zr, withZ, s.rowbits, m, kk - before);
-                } else {
-                    kk -= tot;
+                if (alive[k]) {
+                    const int nxt = rank[k] + 1 < total ? lds->packed[rank[k] + 1].x : INT_MIN;
+                    if (!(ekey[k] > bound && ekey[k] > nxt)) firstbad = min(firstbad, rank[k]);
                 }
             }
-        }
-        // apply the selection (a failed selection leaves the slot untouched)
-        if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
-        if (l == (selc & 63)) out[selc] = (uint8_t)selr;
-        if (l == (selr & 63)) s.rowbits &= ~(1u << (selr >> 6));
+            const int run = min(wave_min_i32(firstbad), total);
+            if (run > 0) {
 #pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            if (selc == l + kWave * k) s.cal[k] = false;
-            if (s.cal[k]) {
-                if (s.zr[k] == selr) s.zal[k] = false;
-                // the cached row left, or the cached value was tied: bound only
-                if (!s.stale[k] && (s.nzr[k] == selr || s.nzc[k] > 1)) s.stale[k] = true;
+                for (int k = 0; k < CPL; ++k)
+                    if (alive[k] && rank[k] < run) {
+                        const int c = epay[k] & 0xff, zr = epay[k] >> 8;
+                        out[c] = (uint8_t)zr;
+                        lds->deadcol[c] = 1;
+                        lds->deadrow[zr] = 1;
+                    }
+                i += run;
             }
+            wave_lds_sync();
+            if (i >= n) break;
         }
+        // ---- one exact selection
+        st_sync<CPL>(n, s, lds);
+        int selr;
+        const int selc = st_generic_pick<CPL>(n, i, false, V, Vs, s, seed, iter, member, swarm, selr);
+        ++i;
+        if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
+        if (l == 0) { out[selc] = (uint8_t)selr; lds->deadcol[selc] = 1; lds->deadrow[selr] = 1; }
+        st_apply<CPL>(s, selc, selr);
+        wave_lds_sync();
     }
 }
 
