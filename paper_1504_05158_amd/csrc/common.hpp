@@ -35,6 +35,7 @@ struct InstDesc {
     int ls;         // one pair exchange per iteration
     int migrate, migr_d, period;
     int sym;        // F and D both symmetric
+    int zd;         // F and D both have a zero diagonal
     int path;       // 1 int8 MFMA, 2 int32
     uint64_t seed;
     // instance data

@@ -76,10 +76,10 @@ struct RowInfo {
 // Stage C for one permutation held in LDS (sp, NP bytes, entries >= n are 0).
 // Returns the goal; bestkey = (delta << 16) | (x << 8) | y of the first
 // minimum pair (LLONG_MAX if n < 2).  If dout != NULL every delta is written.
-template <int NP, bool SYM>
+template <int NP, bool SYM, bool ZD>
 __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const int8_t* sFT, const int8_t* sDT,
-                                const uint8_t* sp, RowInfo* sri, bool want_pairs, long long* dout,
-                                long long& goal, long long& bestkey)
+                                const uint8_t* sp, RowInfo* sri, bool want_pairs, long long* dout, long long& goal,
+                                long long& bestkey)
 {
     constexpr int T = NP / 32;
     const int l = lane_id(), h = l >> 5, lc = l & 31;
@@ -153,16 +153,21 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             __builtin_amdgcn_sched_barrier(0);
             if (y >= n) continue;
             const RowInfo cy = sri[y];
+            const int ybits = y;  // low byte of the key
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int x = 32 * a + tile_row(i, h);
-                if (x >= y) continue;
+                if (x >= y) continue;  // (a data-dependent branch here also keeps register use down)
                 const RowInfo rx = sri[x];
                 const int fxy = sF[x * NP + y];
                 const int dxy = sD[rx.p * NP + cy.p];
                 int del;
                 if constexpr (SYM) {
-                    del = 2 * (A[i] + AT[i]) - rx.da - cy.da + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
+                    const int base = 2 * (A[i] + AT[i]) - rx.da - cy.da;
+                    if constexpr (ZD)
+                        del = base + 4 * fxy * dxy;
+                    else
+                        del = base + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
                 } else {
                     const int fyx = sF[y * NP + x];
                     const int dyx = sD[cy.p * NP + rx.p];
@@ -176,7 +181,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     dout[(size_t)x * n + y] = del;
                     dout[(size_t)y * n + x] = del;
                 }
-                const long long key = ((long long)del << 16) | (x << 8) | y;
+                // (delta, x, y) as one ordered 64-bit key: delta * 2^16 + x * 2^8 + y
+                const long long key = ((long long)del << 16) | (x << 8) | ybits;
                 bestkey = key < bestkey ? key : bestkey;
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -215,7 +221,7 @@ __device__ __forceinline__ float clampv(float t, float vmax) { return fminf(fmax
 __device__ __forceinline__ float stream_column(const float* __restrict__ vp, float* __restrict__ vq, int n, float sc,
                                                float c1, float vmax, float& m1, int& r1, float& m2)
 {
-    constexpr int B = 16;
+    constexpr int B = 32;
     float sum = 0.0f;
     int r0 = 0;
     for (; r0 + B <= n; r0 += B) {
@@ -250,7 +256,7 @@ __device__ __forceinline__ float stream_column(const float* __restrict__ vp, flo
 }  // namespace
 
 // ------------------------------------------------------------------ fused step
-template <int NP, bool SYM>
+template <int NP, bool SYM, bool ZD>
 __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 {
     constexpr int CPL = NP <= 64 ? 1 : NP <= 128 ? 2 : 4;  // column slots per lane
@@ -349,7 +355,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 
     // ---- C. goal, pair-exchange deltas, one exchange
     long long goal, key;
-    goal_delta_mfma<NP, SYM>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
+    goal_delta_mfma<NP, SYM, ZD>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
     int ba = -1, bb = -1;
     if (d.ls && key != LLONG_MAX) {
         const long long del = key >> 16;
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 }
 
 // ------------------------------------------------------------------ eval
-template <int NP, bool SYM>
+template <int NP, bool SYM, bool ZD>
 __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __restrict__ perms, int count,
                                                    long long* __restrict__ goals, long long* __restrict__ deltas)
 {
@@ -398,23 +404,25 @@ __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __
     wave_sync();
     long long* dout = deltas ? deltas + (size_t)e * n * n : nullptr;
     long long goal, key;
-    goal_delta_mfma<NP, SYM>(n, sF, sD, sFT, sDT, pw, sri[w], dout != nullptr, dout, goal, key);
+    goal_delta_mfma<NP, SYM, ZD>(n, sF, sD, sFT, sDT, pw, sri[w], dout != nullptr, dout, goal, key);
     if (dout)
         for (int j = l; j < n; j += kWave) dout[(size_t)j * n + j] = 0;
     if (l == 0) goals[e] = goal;
 }
 
 // ------------------------------------------------------------------ launchers
-template <bool SYM>
+// Contraction variants: general (F or D not symmetric), symmetric, symmetric
+// with zero diagonals.
+template <bool SYM, bool ZD>
 static hipError_t fused_launch_np(const InstDesc& d, hipStream_t st)
 {
     const dim3 grid((unsigned)((d.P + kWaves - 1) / kWaves)), block(kWaves * kWave);
     switch (d.npad) {
-    case 32: hipLaunchKernelGGL((k_fused_step<32, SYM>), grid, block, 0, st, d); break;
-    case 64: hipLaunchKernelGGL((k_fused_step<64, SYM>), grid, block, 0, st, d); break;
-    case 96: hipLaunchKernelGGL((k_fused_step<96, SYM>), grid, block, 0, st, d); break;
-    case 128: hipLaunchKernelGGL((k_fused_step<128, SYM>), grid, block, 0, st, d); break;
-    case 160: hipLaunchKernelGGL((k_fused_step<160, SYM>), grid, block, 0, st, d); break;
+    case 32: hipLaunchKernelGGL((k_fused_step<32, SYM, ZD>), grid, block, 0, st, d); break;
+    case 64: hipLaunchKernelGGL((k_fused_step<64, SYM, ZD>), grid, block, 0, st, d); break;
+    case 96: hipLaunchKernelGGL((k_fused_step<96, SYM, ZD>), grid, block, 0, st, d); break;
+    case 128: hipLaunchKernelGGL((k_fused_step<128, SYM, ZD>), grid, block, 0, st, d); break;
+    case 160: hipLaunchKernelGGL((k_fused_step<160, SYM, ZD>), grid, block, 0, st, d); break;
     default: return hipErrorNotSupported;
     }
     return hipGetLastError();
@@ -426,7 +434,8 @@ hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipE
 {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
-    e = d.sym ? fused_launch_np<true>(d, st) : fused_launch_np<false>(d, st);
+    e = !d.sym ? fused_launch_np<false, false>(d, st)
+               : d.zd ? fused_launch_np<true, true>(d, st) : fused_launch_np<true, false>(d, st);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[7], st)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[8], st)) != hipSuccess) return e;
@@ -436,17 +445,17 @@ hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipE
     return hipSuccess;
 }
 
-template <bool SYM>
+template <bool SYM, bool ZD>
 static hipError_t eval_launch_np(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
                                  long long* deltas, hipStream_t st)
 {
     const dim3 grid((unsigned)((count + kWaves - 1) / kWaves)), block(kWaves * kWave);
     switch (d.npad) {
-    case 32: hipLaunchKernelGGL((k_eval_mfma<32, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 64: hipLaunchKernelGGL((k_eval_mfma<64, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 96: hipLaunchKernelGGL((k_eval_mfma<96, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 128: hipLaunchKernelGGL((k_eval_mfma<128, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 160: hipLaunchKernelGGL((k_eval_mfma<160, SYM>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 32: hipLaunchKernelGGL((k_eval_mfma<32, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 64: hipLaunchKernelGGL((k_eval_mfma<64, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 96: hipLaunchKernelGGL((k_eval_mfma<96, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 128: hipLaunchKernelGGL((k_eval_mfma<128, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 160: hipLaunchKernelGGL((k_eval_mfma<160, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
     default: return hipErrorNotSupported;
     }
     return hipGetLastError();
@@ -456,8 +465,9 @@ hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, 
                             hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    return d.sym ? eval_launch_np<true>(d, perms, count, goals, deltas, st)
-                 : eval_launch_np<false>(d, perms, count, goals, deltas, st);
+    return !d.sym ? eval_launch_np<false, false>(d, perms, count, goals, deltas, st)
+                  : d.zd ? eval_launch_np<true, true>(d, perms, count, goals, deltas, st)
+                         : eval_launch_np<true, false>(d, perms, count, goals, deltas, st);
 }
 
 }  // namespace qap

@@ -99,11 +99,13 @@ int check_params(const qap_instance* in, const qap_params* p)
 
 // Range check and path choice.  int8 MFMA needs every entry in [-128, 127];
 // any exact int32 contraction needs n * max|F| * max|D| < 2^31.
-int choose_path(const qap_instance* in, const qap_params* p, int engine, int* path, int* sym, int* mul24)
+int choose_path(const qap_instance* in, const qap_params* p, int engine, int* path, int* sym, int* mul24,
+                int* zd)
 {
     const int n = in->n;
     long long mf = 0, md = 0;
-    bool f8 = true, s = true;
+    bool f8 = true, s = true, z = true;
+    for (int i = 0; i < n; ++i) z = z && in->F[i * n + i] == 0 && in->D[i * n + i] == 0;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
             const long long f = in->F[i * n + j], dd = in->D[i * n + j];
@@ -126,11 +128,12 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
     *path = pth;
     *sym = s ? 1 : 0;
     *mul24 = (mf < (1LL << 23) && md < (1LL << 23)) ? 1 : 0;
+    *zd = z ? 1 : 0;
     return QAP_OK;
 }
 
 int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_params* p, int path, int sym,
-                   int mul24)
+                   int mul24, int zd)
 {
     const int n = in->n;
     InstDesc& d = I.d;
@@ -152,6 +155,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     d.migr_d = d.migrate ? (int)(p->migration_factor * (float)I.m) : 0;
     d.period = p->migration_period < 1 ? 1 : p->migration_period;
     d.sym = sym;
+    d.zd = zd;
     d.path = path;
     d.seed = p->seed;
     const size_t nn = (size_t)n * n, P = (size_t)I.P;
@@ -318,12 +322,13 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     *out = nullptr;
     if (!insts || !prms || count < 1) return QAP_ERR_INVALID_ARG;
     // every host-side check comes before the first HIP call
-    std::vector<int> path((size_t)count), sym((size_t)count), mul24((size_t)count);
+    std::vector<int> path((size_t)count), sym((size_t)count), mul24((size_t)count), zd((size_t)count);
     for (int k = 0; k < count; ++k) {
         int rc = check_params(&insts[k], &prms[k]);
         if (rc != QAP_OK) return rc;
         if (prms[k].engine != prms[0].engine) return QAP_ERR_INVALID_ARG;
-        rc = choose_path(&insts[k], &prms[k], prms[0].engine, &path[(size_t)k], &sym[(size_t)k], &mul24[(size_t)k]);
+        rc = choose_path(&insts[k], &prms[k], prms[0].engine, &path[(size_t)k], &sym[(size_t)k], &mul24[(size_t)k],
+                         &zd[(size_t)k]);
         if (rc != QAP_OK) return rc;
     }
     qap_swarm* h = new (std::nothrow) qap_swarm();
@@ -342,7 +347,7 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     h->inst.resize((size_t)count);
     for (int k = 0; k < count; ++k) {
         const int rc = setup_instance(h, h->inst[(size_t)k], &insts[k], &prms[k], path[(size_t)k], sym[(size_t)k],
-                                      mul24[(size_t)k]);
+                                      mul24[(size_t)k], zd[(size_t)k]);
         if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
     }
     *out = h;
