@@ -14,8 +14,10 @@ the timed region.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -40,6 +42,47 @@ def algorithmic_bytes(stage: str, n: int) -> int:
     if stage == "goal_delta":  # X' read, X write, P^L read, goal, P^L goal
         return 3 * n + 24
     return 0
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_n128x10k_traffic.md")
+KERNEL_SOURCES = ["common.hpp", "philox.hpp", "second_target.hpp", "kernels_fused.hip"]
+
+
+def kernel_hash() -> str:
+    """Hash of the sources the fused step kernel is built from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1504_05158_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a copy
+    of known size), or None if absent or taken on other kernel sources."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source hash:\s*`?([0-9a-f]+)", text)
+    t = re.search(r"scaled HBM bytes per launch:\s*([0-9.e+]+)", text)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def traffic_calibration(size_mib: int = 1024, reps: int = 3) -> None:
+    """A plain device copy of known size (size_mib read + written per
+    launch) for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = size_mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": size_mib * (1 << 20), "launches": reps}))
 
 
 def contraction_ops(n: int, sym: bool) -> int:
@@ -85,8 +128,12 @@ def run_gpu(args, engine: str):
     else:
         bpl = algorithmic_bytes(dom, n) * P
         achieved = bpl / (avg_ms * 1e-3) / 1e9
+        traffic = measured_traffic() if (dom == "fused" and engine == "fused") else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None)
+                    frac=round(achieved / HBM_PEAK_GBS, 4),
+                    traffic=None if traffic is None else round(traffic / 1e9, 4))
+        roof["algorithmic_gb_per_launch"] = round(bpl / 1e9, 4)
+        roof["traffic_unit"] = "GB per launch"
     roof["kernel"] = dom
     roof["avg_ms"] = round(avg_ms, 4)
     return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, roofline=roof,
@@ -126,9 +173,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--engine", default="plain", choices=["fused", "plain"])
-    ap.add_argument("--compare", action="store_true", help="also time the other engine")
+    ap.add_argument("--engine", default="fused", choices=["fused", "plain"])
+    ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-calibration", action="store_true",
+                    help="run only a 1 GiB device copy (for scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
@@ -140,9 +189,12 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.traffic_calibration:
+        traffic_calibration()
+        return
     res = run_gpu(args, args.engine)
     other = None
-    if args.compare:
+    if not args.no_compare:
         oth = "plain" if args.engine == "fused" else "fused"
         try:
             other = run_gpu(args, oth)

@@ -13,8 +13,10 @@
 // rows (value, first row, count).  The cache is an upper bound once one of
 // its rows may have gone ("stale"); it is recomputed by the whole wave
 // (one read of the column) only when the column's bound reaches the current
-// maximum.  A selection is then one wave max plus a ballot, O(n) per
-// particle-iteration instead of the O(n^3) scans of the plain procedure.
+// maximum.  After the first `depth` selections, the Z cells above every non-Z
+// key are taken together; the exact selection (one wave max plus a ballot) is
+// needed only between such groups, a few times per particle-iteration, instead
+// of the n scans of the remaining matrix of the plain procedure (O(n^3)).
 #pragma once
 #include "common.hpp"
 #include "philox.hpp"
@@ -137,21 +139,18 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
     }
 }
 
-// Per-wave LDS scratch of the selection: the sorted Z cells, their compacted
-// alive subsequence, and dead-row / dead-column flags.
+// Per-wave LDS scratch of the selection: dead-row / dead-column flags.
 template <int S>
 struct StLds {
-    int2 sorted[kWave * S];
-    int2 packed[kWave * S];
     uint8_t deadrow[kMaxN];
     uint8_t deadcol[kMaxN];
 };
 
-// Float -> int with the same order (signed compare); -0 is folded into +0 first.
-__device__ __forceinline__ int ordered_key(float f)
+__device__ __forceinline__ void wave_lds_sync()
 {
-    int i = __float_as_int(f + 0.0f);
-    return i ^ ((i >> 31) & 0x7fffffff);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // One selection by the exact procedure: returns the column (uniform) and
@@ -293,7 +292,8 @@ __device__ __forceinline__ void st_sync(int n, StState<CPL>& s, const L* lds)
     }
 }
 
-// Largest non-Z bound over the alive columns (an upper bound of every non-Z key).
+// Largest non-Z bound over the alive columns (an upper bound of every non-Z
+// key; -inf when no alive column has a non-Z cell left).
 template <int CPL>
 __device__ __forceinline__ float st_nonz_bound(const StState<CPL>& s)
 {
@@ -306,89 +306,20 @@ __device__ __forceinline__ float st_nonz_bound(const StState<CPL>& s)
 
 // Run the n selections.  Writes out[c] = chosen row for every column c < n.
 // The first `depth` selections (Z cells excluded) use the exact procedure.
-// Afterwards the Z cells are sorted by key once; the best alive Z cell is
-// taken directly whenever its key beats both the next alive Z key and the
-// bound of all non-Z keys (then it is the unique maximum); otherwise the exact
-// procedure makes the selection.
-// Bitonic sort (descending by key, then ascending payload) of the 64*S
-// entries held as (key, payload) per slot and lane; writes them to LDS.  Kept
-// out of line: unrolled into the fused kernel it inflates register pressure.
-template <int S>
-__device__ __noinline__ void st_sort_desc(int2* sorted, int k0, int p0, int k1, int p1, int k2, int p2, int k3,
-                                          int p3)
-{
-    constexpr int NS = kWave * S;
-    const int l = lane_id();
-    int key[S], pay[S];
-    key[0] = k0; pay[0] = p0;
-    if constexpr (S > 1) { key[1] = k1; pay[1] = p1; }
-    if constexpr (S > 2) { key[2] = k2; pay[2] = p2; key[3] = k3; pay[3] = p3; }
-#pragma unroll
-    for (int size = 2; size <= NS; size <<= 1) {
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            int nk[S], np[S];
-#pragma unroll
-            for (int k = 0; k < S; ++k) {
-                int pk, pp;
-                if (stride < kWave) {
-                    pk = __shfl_xor(key[k], stride, kWave);
-                    pp = __shfl_xor(pay[k], stride, kWave);
-                } else {
-                    pk = key[k ^ (stride / kWave)];
-                    pp = pay[k ^ (stride / kWave)];
-                }
-                const int e = k * kWave + l;
-                const bool lower = (e & stride) == 0;
-                const bool desc = (e & size) == 0;
-                const bool self_first = key[k] > pk || (key[k] == pk && pay[k] < pp);
-                const bool keep = (lower == desc) ? self_first : !self_first;
-                nk[k] = keep ? key[k] : pk;
-                np[k] = keep ? pay[k] : pp;
-            }
-#pragma unroll
-            for (int k = 0; k < S; ++k) { key[k] = nk[k]; pay[k] = np[k]; }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < S; ++k) sorted[k * kWave + l] = make_int2(key[k], pay[k]);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ int wave_min_i32(int v)
-{
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off, kWave));
-    return v;
-}
-
-// Run the n selections.  Writes out[c] = chosen row for every column c < n.
-// The first `depth` selections (Z cells excluded) use the exact procedure.
-// Afterwards the Z cells are sorted by key once.  Taking a Z cell never
-// removes another Z cell (they share no row or column), and the bound on all
-// non-Z keys only falls, so from any state the selections that take the best
-// alive Z cell -- allowed while its key beats both the next alive Z key and
-// that bound, i.e. while it is the unique maximum -- form a run that is decided
-// at once: the alive sorted entries are compacted, each is compared with its
-// successor and the bound, and the longest acceptable prefix is taken.  The
-// selection after a run (a tie, or a non-Z cell that may win) uses the exact
-// procedure, then a new run starts.  lds: the wave's scratch.
+// Afterwards: taking a Z cell never removes another Z cell (they share no row
+// or column), and every non-Z key is bounded by the largest cached non-Z
+// bound, which only falls.  So all alive Z cells whose key exceeds that bound
+// are exactly the next selections, in some order -- ties among them only
+// reorder picks that are all taken -- and they are taken at once.  The
+// selection after them (a non-Z cell or a Z cell not above the bound) uses
+// the exact procedure, then the bound is recomputed and the next group taken.
+// lds: the wave's scratch.
 template <int CPL>
 __device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
                           StState<CPL>& s, uint8_t* out, StLds<CPL>* lds, uint64_t seed, uint32_t iter,
                           uint32_t member, uint32_t swarm)
 {
     static_assert(CPL == 1 || CPL == 2 || CPL == 4, "column slots per lane must be 1, 2 or 4");
-    constexpr int NS = kWave * CPL;  // sort length, a power of two
     const int l = lane_id();
     for (int r = l; r < kMaxN; r += kWave) { lds->deadrow[r] = 0; lds->deadcol[r] = 0; }
     wave_lds_sync();
@@ -400,68 +331,28 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
         if (l == 0) { out[selc] = (uint8_t)selr; lds->deadcol[selc] = 1; lds->deadrow[selr] = 1; }
         st_apply<CPL>(s, selc, selr);
     }
-    if (i >= n) return;
-    // sorted Z cells (descending key), payload = column | Z row << 8
-    {
-        int kz[4] = {INT_MIN, INT_MIN, INT_MIN, INT_MIN}, pz[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int k = 0; k < CPL; ++k) {
-            kz[k] = (s.cal[k] && s.zal[k]) ? ordered_key(s.zk[k]) : INT_MIN;
-            pz[k] = (l + kWave * k) | ((s.zr[k] & 0xff) << 8);
-        }
-        st_sort_desc<CPL>(lds->sorted, kz[0], pz[0], kz[1], pz[1], kz[2], pz[2], kz[3], pz[3]);
-    }
-    int ekey[CPL], epay[CPL];
-#pragma unroll
-    for (int k = 0; k < CPL; ++k) {
-        const int2 e = lds->sorted[k * kWave + l];
-        ekey[k] = e.x;
-        epay[k] = e.y;
-    }
-    const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
     wave_lds_sync();
     while (i < n) {
-        // ---- a run of Z cells taken at once
-        const int bound = ordered_key(st_nonz_bound<CPL>(s));
-        bool alive[CPL];
-        int rank[CPL], total = 0;
+        // ---- every alive Z cell above the non-Z bound, at once
+        const float bound = st_nonz_bound<CPL>(s);
+        int taken = 0;
 #pragma unroll
         for (int k = 0; k < CPL; ++k) {
-            alive[k] = ekey[k] != INT_MIN && !lds->deadcol[epay[k] & 0xff] && !lds->deadrow[epay[k] >> 8];
-            const uint64_t b = ballot64(alive[k]);
-            rank[k] = total + __popcll(b & below);
-            total += __popcll(b);
-        }
-        if (total > 0) {
-#pragma unroll
-            for (int k = 0; k < CPL; ++k)
-                if (alive[k]) lds->packed[rank[k]] = make_int2(ekey[k], epay[k]);
-            wave_lds_sync();
-            int firstbad = INT_MAX;
-#pragma unroll
-            for (int k = 0; k < CPL; ++k) {
-                if (alive[k]) {
-                    const int nxt = rank[k] + 1 < total ? lds->packed[rank[k] + 1].x : INT_MIN;
-                    if (!(ekey[k] > bound && ekey[k] > nxt)) firstbad = min(firstbad, rank[k]);
-                }
+            const bool take = s.cal[k] && s.zal[k] && s.zk[k] > bound;
+            taken += __popcll(ballot64(take));
+            if (take) {
+                const int c = l + kWave * k, zr = s.zr[k];
+                out[c] = (uint8_t)zr;
+                lds->deadcol[c] = 1;
+                lds->deadrow[zr] = 1;
+                s.cal[k] = false;
             }
-            const int run = min(wave_min_i32(firstbad), total);
-            if (run > 0) {
-#pragma unroll
-                for (int k = 0; k < CPL; ++k)
-                    if (alive[k] && rank[k] < run) {
-                        const int c = epay[k] & 0xff, zr = epay[k] >> 8;
-                        out[c] = (uint8_t)zr;
-                        lds->deadcol[c] = 1;
-                        lds->deadrow[zr] = 1;
-                    }
-                i += run;
-            }
-            wave_lds_sync();
-            if (i >= n) break;
         }
+        i += taken;
+        if (i >= n) break;
+        wave_lds_sync();
+        if (taken) st_sync<CPL>(n, s, lds);
         // ---- one exact selection
-        st_sync<CPL>(n, s, lds);
         int selr;
         const int selc = st_generic_pick<CPL>(n, i, false, V, Vs, s, seed, iter, member, swarm, selr);
         ++i;
