@@ -38,26 +38,38 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 16 bytes Dm[py][p[kb + j]], j = 0..15, packed little-endian into 4 ints.
-__device__ __forceinline__ v4i gather16(const int8_t* Dm, int np, int py, const uint8_t* p, int kb)
+// LDS row stride of the n x n int8 matrices: 16 bytes of padding put the 16-byte
+// fragments of 8 consecutive rows in 8 distinct 4-bank groups (conflict-free
+// ds_read_b128).
+template <int NP>
+constexpr int lds_stride() { return NP + 16; }
+
+// 16 bytes Mt[p[kb + j]][py], j = 0..15, packed little-endian into 4 ints:
+// with Mt the transpose of M this is M[py][p[kb + j]].  For a fixed j every
+// lane of a half-wave reads the same row (kb does not depend on the lane) at
+// its own column, which spreads the byte reads over the banks; reading row py
+// of M instead would send all 32 lanes to one bank.
+template <int LS>
+__device__ __forceinline__ v4i gather16(const int8_t* Mt, int py, const uint8_t* p, int kb)
 {
     const v4i pk = *reinterpret_cast<const v4i*>(p + kb);
-    const uint8_t* row = reinterpret_cast<const uint8_t*>(Dm) + py * np;
+    const uint8_t* col = reinterpret_cast<const uint8_t*>(Mt) + py;
     v4i out;
 #pragma unroll
     for (int w = 0; w < 4; ++w) {
         const uint32_t word = (uint32_t)pk[w];
         uint32_t r = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) r |= (uint32_t)row[(word >> (8 * b)) & 0xffu] << (8 * b);
+        for (int b = 0; b < 4; ++b) r |= (uint32_t)col[((word >> (8 * b)) & 0xffu) * LS] << (8 * b);
         out[w] = (int)r;
     }
     return out;
 }
 
-__device__ __forceinline__ v4i frag16(const int8_t* M, int np, int row, int kb)
+template <int LS>
+__device__ __forceinline__ v4i frag16(const int8_t* M, int row, int kb)
 {
-    return *reinterpret_cast<const v4i*>(M + row * np + kb);
+    return *reinterpret_cast<const v4i*>(M + row * LS + kb);
 }
 
 __device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c)
@@ -81,9 +93,10 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                                 const uint8_t* sp, RowInfo* sri, bool want_pairs, long long* dout, long long& goal,
                                 long long& bestkey)
 {
-    constexpr int T = NP / 32;
+    constexpr int T = NP / 32, LS = lds_stride<NP>();
     const int l = lane_id(), h = l >> 5, lc = l & 31;
-    // Dp (and Dp' for the general case) fragments for every (block, K chunk)
+    // Dp (and Dp' for the general case) fragments for every (block, K chunk):
+    // Dp[y][k] = D[p_y][p_k] = D^T[p_k][p_y], Dp'[y][k] = D^T[p_y][p_k] = D[p_k][p_y]
     v4i dp[T][T];
     v4i dpt[SYM ? 1 : T][SYM ? 1 : T];
 #pragma unroll
@@ -92,8 +105,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
         const int py = y < n ? (int)sp[y] : 0;
 #pragma unroll
         for (int kc = 0; kc < T; ++kc) {
-            dp[b][kc] = y < n ? gather16(sD, NP, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
-            if constexpr (!SYM) dpt[b][kc] = y < n ? gather16(sDT, NP, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            dp[b][kc] = y < n ? gather16<LS>(SYM ? sD : sDT, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            if constexpr (!SYM) dpt[b][kc] = y < n ? gather16<LS>(sD, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
         }
     }
     // diagonal tiles: A_xx (and B_xx) -> row info, goal = trace(A)
@@ -104,8 +117,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
         v16i accb = {};
 #pragma unroll
         for (int kc = 0; kc < T; ++kc) {
-            acc = mfma32(frag16(sF, NP, 32 * a + lc, 32 * kc + 16 * h), dp[a][kc], acc);
-            if constexpr (!SYM) accb = mfma32(frag16(sFT, NP, 32 * a + lc, 32 * kc + 16 * h), dpt[a][kc], accb);
+            acc = mfma32(frag16<LS>(sF, 32 * a + lc, 32 * kc + 16 * h), dp[a][kc], acc);
+            if constexpr (!SYM) accb = mfma32(frag16<LS>(sFT, 32 * a + lc, 32 * kc + 16 * h), dpt[a][kc], accb);
         }
         if (h == ((lc >> 2) & 1)) {
             const int want = 4 * (lc >> 3) + (lc & 3);
@@ -119,8 +132,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 const int px = sp[x];
                 RowInfo ri;
                 ri.p = px;
-                ri.f = sF[x * NP + x];
-                ri.dp = sD[px * NP + px];
+                ri.f = sF[x * LS + x];
+                ri.dp = sD[px * LS + px];
                 ri.da = SYM ? 2 * da : da + db;
                 sri[x] = ri;
             }
@@ -139,13 +152,13 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             v16i A = {}, AT = {}, B = {}, BT = {};
 #pragma unroll
             for (int kc = 0; kc < T; ++kc) {
-                const v4i fa = frag16(sF, NP, 32 * a + lc, 32 * kc + 16 * h);
-                const v4i fb = frag16(sF, NP, 32 * b + lc, 32 * kc + 16 * h);
+                const v4i fa = frag16<LS>(sF, 32 * a + lc, 32 * kc + 16 * h);
+                const v4i fb = frag16<LS>(sF, 32 * b + lc, 32 * kc + 16 * h);
                 A = mfma32(fa, dp[b][kc], A);     // A[x][y]  = sum_k F[x][k] Dp[y][k]
                 AT = mfma32(dp[a][kc], fb, AT);   // AT[x][y] = sum_k Dp[x][k] F[y][k] = A[y][x]
                 if constexpr (!SYM) {
-                    const v4i ga = frag16(sFT, NP, 32 * a + lc, 32 * kc + 16 * h);
-                    const v4i gb = frag16(sFT, NP, 32 * b + lc, 32 * kc + 16 * h);
+                    const v4i ga = frag16<LS>(sFT, 32 * a + lc, 32 * kc + 16 * h);
+                    const v4i gb = frag16<LS>(sFT, 32 * b + lc, 32 * kc + 16 * h);
                     B = mfma32(ga, dpt[b][kc], B);
                     BT = mfma32(dpt[a][kc], gb, BT);
                 }
@@ -159,8 +172,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 const int x = 32 * a + tile_row(i, h);
                 if (x >= y) continue;  // (a data-dependent branch here also keeps register use down)
                 const RowInfo rx = sri[x];
-                const int fxy = sF[x * NP + y];
-                const int dxy = sD[rx.p * NP + cy.p];
+                const int fxy = sF[x * LS + y];
+                const int dxy = sD[rx.p * LS + cy.p];
                 int del;
                 if constexpr (SYM) {
                     const int base = 2 * (A[i] + AT[i]) - rx.da - cy.da;
@@ -169,8 +182,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     else
                         del = base + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
                 } else {
-                    const int fyx = sF[y * NP + x];
-                    const int dyx = sD[cy.p * NP + rx.p];
+                    const int fyx = sF[y * LS + x];
+                    const int dyx = sD[cy.p * LS + rx.p];
                     const int faa = rx.f, fbb = cy.f, daa = rx.dp, dbb = cy.dp;
                     const int kap = (faa - fyx) * (dyx - daa) + (fxy - fbb) * (dbb - dxy) + (faa - fxy) * (dxy - daa) +
                                     (fyx - fbb) * (dbb - dyx);
@@ -199,15 +212,16 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
 template <int NP, bool SYM>
 __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF, int8_t* sD, int8_t* sFT, int8_t* sDT)
 {
-    const int nv = NP * NP / 16;
+    constexpr int LS = lds_stride<NP>(), RV = NP / 16;  // 16-byte chunks per row
     const v4i* F = reinterpret_cast<const v4i*>(d.F8);
     const v4i* D = reinterpret_cast<const v4i*>(d.D8);
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) {
-        reinterpret_cast<v4i*>(sF)[i] = F[i];
-        reinterpret_cast<v4i*>(sD)[i] = D[i];
+    for (int i = threadIdx.x; i < NP * RV; i += blockDim.x) {
+        const int o = (i / RV) * LS + 16 * (i % RV);
+        *reinterpret_cast<v4i*>(sF + o) = F[i];
+        *reinterpret_cast<v4i*>(sD + o) = D[i];
         if constexpr (!SYM) {
-            reinterpret_cast<v4i*>(sFT)[i] = reinterpret_cast<const v4i*>(d.FT8)[i];
-            reinterpret_cast<v4i*>(sDT)[i] = reinterpret_cast<const v4i*>(d.DT8)[i];
+            *reinterpret_cast<v4i*>(sFT + o) = reinterpret_cast<const v4i*>(d.FT8)[i];
+            *reinterpret_cast<v4i*>(sDT + o) = reinterpret_cast<const v4i*>(d.DT8)[i];
         }
     }
 }
@@ -260,10 +274,10 @@ template <int NP, bool SYM, bool ZD>
 __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 {
     constexpr int CPL = NP <= 64 ? 1 : NP <= 128 ? 2 : 4;  // column slots per lane
-    __shared__ __attribute__((aligned(16))) int8_t sF[NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sD[NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
     __shared__ RowInfo sri[kWaves][NP];
     __shared__ StLds<CPL> slds[kWaves];
@@ -387,10 +401,10 @@ template <int NP, bool SYM, bool ZD>
 __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __restrict__ perms, int count,
                                                    long long* __restrict__ goals, long long* __restrict__ deltas)
 {
-    __shared__ __attribute__((aligned(16))) int8_t sF[NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sD[NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * NP];
-    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * NP];
+    __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
     __shared__ RowInfo sri[kWaves][NP];
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
@@ -427,6 +441,7 @@ static hipError_t fused_launch_np(const InstDesc& d, hipStream_t st)
     }
     return hipGetLastError();
 }
+
 
 bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160; }
 

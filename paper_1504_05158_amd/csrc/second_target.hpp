@@ -242,7 +242,10 @@ __device__ int st_generic_pick(int n, int i, bool skipZ, const float* __restrict
                 const int zr = readlane_i32(s.zr[k], owner);
                 const bool withZ = !skipZ && readlane_i32((int)s.zal[k], owner);
                 selc = c;
-                selr = st_kth_tied_row<CPL>(n, V, Vs, c, zr, withZ, s.rowbits, m, kk - before);
+                // a column holding one tied cell has its row in the (exact) cache
+                selr = readlane_i32(cc[k], owner) == 1
+                           ? readlane_i32(cr[k], owner)
+                           : st_kth_tied_row<CPL>(n, V, Vs, c, zr, withZ, s.rowbits, m, kk - before);
             } else {
                 kk -= tot;
             }
