@@ -166,14 +166,20 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             __builtin_amdgcn_sched_barrier(0);
             if (y >= n) continue;
             const RowInfo cy = sri[y];
-            const int ybits = y;  // low byte of the key
+            // lane rows x = 32a + 4h + xo(i), xo(i) = 8(i/4) + i%4, increasing in i:
+            // the first strict minimum over i is the lexicographic (delta, x) minimum
+            const RowInfo* rxb = sri + 32 * a + 4 * h;
+            const int8_t* fxb = sF + (32 * a + 4 * h) * LS + y;
+            const int8_t* fyb = sF + y * LS + 32 * a + 4 * h;
+            const int8_t* dyb = sD + cy.p;
+            int tmin = INT_MAX, ti = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int x = 32 * a + tile_row(i, h);
-                if (x >= y) continue;  // (a data-dependent branch here also keeps register use down)
-                const RowInfo rx = sri[x];
-                const int fxy = sF[x * LS + y];
-                const int dxy = sD[rx.p * LS + cy.p];
+                const int xo = 8 * (i >> 2) + (i & 3);
+                if (a == b && 32 * a + 4 * h + xo >= y) continue;  // diagonal tiles: x < y only
+                const RowInfo rx = rxb[xo];
+                const int fxy = fxb[xo * LS];
+                const int dxy = dyb[rx.p * LS];
                 int del;
                 if constexpr (SYM) {
                     const int base = 2 * (A[i] + AT[i]) - rx.da - cy.da;
@@ -182,7 +188,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     else
                         del = base + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
                 } else {
-                    const int fyx = sF[y * LS + x];
+                    const int fyx = fyb[xo];
                     const int dyx = sD[cy.p * LS + rx.p];
                     const int faa = rx.f, fbb = cy.f, daa = rx.dp, dbb = cy.dp;
                     const int kap = (faa - fyx) * (dyx - daa) + (fxy - fbb) * (dbb - dxy) + (faa - fxy) * (dxy - daa) +
@@ -191,11 +197,19 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     del = A[i] + AT[i] + B[i] + BT[i] - rx.da - cy.da - kap + lam;
                 }
                 if (dout) {
+                    const int x = 32 * a + 4 * h + xo;
                     dout[(size_t)x * n + y] = del;
                     dout[(size_t)y * n + x] = del;
                 }
+                const bool lt = del < tmin;
+                tmin = lt ? del : tmin;
+                ti = lt ? i : ti;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (tmin != INT_MAX) {
                 // (delta, x, y) as one ordered 64-bit key: delta * 2^16 + x * 2^8 + y
-                const long long key = ((long long)del << 16) | (x << 8) | ybits;
+                const int x = 32 * a + 4 * h + 8 * (ti >> 2) + (ti & 3);
+                const long long key = ((long long)tmin << 16) | (x << 8) | y;
                 bestkey = key < bestkey ? key : bestkey;
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -226,43 +240,127 @@ __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF,
     }
 }
 
-__device__ __forceinline__ float clampv(float t, float vmax) { return fminf(fmaxf(t, -vmax), vmax); }
+// Clamp to [-vmax, vmax] (S_v); values are finite, so med3 is the clamp.
+__device__ __forceinline__ float clampv(float t, float vmax) { return __builtin_amdgcn_fmed3f(t, -vmax, vmax); }
 
-// One column of the velocity pass: row r of the column is vp[r*n] (the
-// lane's column of V(t)); writes the clamped c1*v to vq[r*n]; returns the sum
-// of |.| and the column's largest value m1 (first row r1) and runner-up m2.
-// Rows are loaded in batches so that many loads are in flight.
-__device__ __forceinline__ float stream_column(const float* __restrict__ vp, float* __restrict__ vq, int n, float sc,
-                                               float c1, float vmax, float& m1, int& r1, float& m2)
+// Rows of X, P^L and P^G in one column and the coefficients of their
+// attraction terms (velocity equation): row xr gets s2 ax + s3 bx, row lr
+// (!= xr) s2 + s3 bl, row gr (!= xr, lr) s3; every other row none.
+struct Attract {
+    int xr, lr, gr;
+    float ax, bx, bl;
+};
+
+// Buffer resource over one particle's n x n matrix (raw, 32-bit elements):
+// row offsets go to the scalar offset, the lane's column to the vector one.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t matrix_rsrc(const float* p, int n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, 4 * n * n, 0x00020000);
+}
+
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 0);
+}
+
+// The attraction cells among rows [lo, hi) of column c: ex, el, eg are the
+// raw V(t) values at rows xr, lr, gr (read only where the row is in range).
+// Each is stored after the plain value of the same cell by the same lane
+// (program order), while its line is still in L2, and replaces that value in
+// the sum.
+__device__ __forceinline__ void fix_cells(__amdgpu_buffer_rsrc_t rq, uint32_t col, uint32_t rowb, int lo, int hi,
+                                          const Attract& at, float ex, float el, float eg, float sc, float c1,
+                                          float s2, float s3, float vmax, float& sum, float& vx)
+{
+    if (at.xr >= lo && at.xr < hi) {
+        const float x = __fmul_rn(ex, sc);
+        const float t = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), __fmul_rn(s2, at.ax)), __fmul_rn(s3, at.bx)), vmax);
+        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        bstore(rq, col + (uint32_t)at.xr * rowb, 0u, t);
+        vx = x;
+    }
+    if (at.lr != at.xr && at.lr >= lo && at.lr < hi) {
+        const float x = __fmul_rn(el, sc);
+        const float t = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), s2), __fmul_rn(s3, at.bl)), vmax);
+        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        bstore(rq, col + (uint32_t)at.lr * rowb, 0u, t);
+    }
+    if (at.gr != at.xr && at.gr != at.lr && at.gr >= lo && at.gr < hi) {
+        const float x = __fmul_rn(eg, sc);
+        const float t = clampv(__fadd_rn(__fmul_rn(c1, x), s3), vmax);
+        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        bstore(rq, col + (uint32_t)at.gr * rowb, 0u, t);
+    }
+}
+
+// Running top two of a column: m1 = max, m2 = runner-up (the middle of m1,
+// m2 and x), u1 = position of the first strict rise of m1 (values finite).
+// Written as compare/select so that the compiler neither canonicalises nor
+// materialises the position: u is a small inline constant.
+__device__ __forceinline__ void top2(float x, int u, float& m1, int& u1, float& m2)
+{
+    const bool le = x <= m1;
+    u1 = le ? u1 : u;
+    m2 = __builtin_amdgcn_fmed3f(m1, m2, x);
+    m1 = le ? m1 : x;
+}
+
+// Column c of the velocity pass over one particle's V(t) (rp) into V(t+1)
+// before the column norm (rq): returns the sum of |.| and the column's
+// largest V(t) value m1 (first row r1), its runner-up m2, and vx = V(t) at
+// the X row.  Rows are loaded in batches so that many loads are in flight;
+// the attraction cells of a batch are read with it and fixed right after it.
+__device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
+                                               float sc, float c1, float s2, float s3, float vmax, const Attract& at,
+                                               float& m1, int& r1, float& m2, float& vx)
 {
     constexpr int B = 32;
+    const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)n;
     float sum = 0.0f;
     int r0 = 0;
     for (; r0 + B <= n; r0 += B) {
         float v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = vp[(size_t)(r0 + u) * n];
+        for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)(r0 + u) * rowb);
+        // attraction rows of this batch (row r0 stands in for absent ones: same lines)
+        const int hi = r0 + B;
+        const float ex = bload(rp, col + (uint32_t)(at.xr >= r0 && at.xr < hi ? at.xr : r0) * rowb, 0u);
+        const float el = bload(rp, col + (uint32_t)(at.lr >= r0 && at.lr < hi ? at.lr : r0) * rowb, 0u);
+        const float eg = bload(rp, col + (uint32_t)(at.gr >= r0 && at.gr < hi ? at.gr : r0) * rowb, 0u);
+        const float mb = m1;
+        int u1 = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const float x = __fmul_rn(v[u], sc);
-            const bool gt = x > m1;
-            m2 = gt ? m1 : fmaxf(m2, x);
-            r1 = gt ? r0 + u : r1;
-            m1 = gt ? x : m1;
+            top2(x, u, m1, u1, m2);
             const float t = clampv(__fmul_rn(c1, x), vmax);
             sum = __fadd_rn(sum, fabsf(t));
-            vq[(size_t)(r0 + u) * n] = t;
+            bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
         }
+        r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
+        fix_cells(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s2, s3, vmax, sum, vx);
     }
+    const int lo = r0;
     for (int r = r0; r < n; ++r) {
-        const float x = __fmul_rn(vp[(size_t)r * n], sc);
-        const bool gt = x > m1;
-        m2 = gt ? m1 : fmaxf(m2, x);
-        r1 = gt ? r : r1;
-        m1 = gt ? x : m1;
+        const float x = __fmul_rn(bload(rp, col, (uint32_t)r * rowb), sc);
+        const float mb = m1;
+        int u1 = 0;
+        top2(x, 0, m1, u1, m2);
+        r1 = m1 != mb ? r : r1;
         const float t = clampv(__fmul_rn(c1, x), vmax);
         sum = __fadd_rn(sum, fabsf(t));
-        vq[(size_t)r * n] = t;
+        bstore(rq, col, (uint32_t)r * rowb, t);
+    }
+    if (lo < n) {
+        const float ex = bload(rp, col + (uint32_t)(at.xr >= lo ? at.xr : lo) * rowb, 0u);
+        const float el = bload(rp, col + (uint32_t)(at.lr >= lo ? at.lr : lo) * rowb, 0u);
+        const float eg = bload(rp, col + (uint32_t)(at.gr >= lo ? at.gr : lo) * rowb, 0u);
+        fix_cells(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s2, s3, vmax, sum, vx);
     }
     return sum;
 }
@@ -284,7 +382,8 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
     __syncthreads();
 
-    const int w = threadIdx.x / kWave, l = lane_id();
+    // wave index made explicitly uniform: every per-particle address lives in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), l = lane_id();
     const int k = blockIdx.x * kWaves + w;
     if (k >= d.P) return;
     const int n = d.n;
@@ -303,6 +402,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     // ---- A. velocity stream + SecondTarget caches
     const float* Sp = d.Vinv[cur] + (size_t)k * n;
     float* Sq = d.Vinv[cur ^ 1] + (size_t)k * n;
+    const __amdgpu_buffer_rsrc_t rp = matrix_rsrc(Vp, n), rq = matrix_rsrc(Vq, n);
     StState<CPL> st;
     st.rowbits = 0;
 #pragma unroll
@@ -312,38 +412,19 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
     for (int kk = 0; kk < CPL; ++kk) {
         const int c = l + kWave * kk;
         const bool on = c < n;
-        int xr = 0, lr = 0, gr = 0;
-        float sc = 1.0f, vx = 0.0f, vl = 0.0f, vg = 0.0f;
-        if (on) {
-            xr = Xk[c];
-            lr = d.PL[(size_t)k * n + c];
-            gr = d.PG[(size_t)g * n + c];
-            sc = Sp[c];
-            vx = __fmul_rn(Vp[(size_t)xr * n + c], sc);
-            vl = __fmul_rn(Vp[(size_t)lr * n + c], sc);
-            vg = __fmul_rn(Vp[(size_t)gr * n + c], sc);
-        }
-        float m1 = -INFINITY, m2 = -INFINITY, sum = 0.0f;
+        int xr = 0;
+        float m1 = -INFINITY, m2 = -INFINITY, sum = 0.0f, vx = 0.0f;
         int r1 = -1;
         if (on) {
-            sum = stream_column(Vp + c, Vq + c, n, sc, c1, vmax, m1, r1, m2);
-            // the (at most three) cells with attraction terms, stored after the
-            // plain value of the same cell by the same lane (program order)
-            const float ax = (float)((xr == lr) - 1), bx = (float)((xr == gr) - 1);
-            const float tx = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vx), __fmul_rn(s2, ax)), __fmul_rn(s3, bx)), vmax);
-            sum = __fadd_rn(sum, fabsf(tx) - fabsf(clampv(__fmul_rn(c1, vx), vmax)));
-            Vq[(size_t)xr * n + c] = tx;
-            if (lr != xr) {
-                const float bl = (float)(lr == gr);
-                const float tl = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, vl), s2), __fmul_rn(s3, bl)), vmax);
-                sum = __fadd_rn(sum, fabsf(tl) - fabsf(clampv(__fmul_rn(c1, vl), vmax)));
-                Vq[(size_t)lr * n + c] = tl;
-            }
-            if (gr != xr && gr != lr) {
-                const float tg = clampv(__fadd_rn(__fmul_rn(c1, vg), s3), vmax);
-                sum = __fadd_rn(sum, fabsf(tg) - fabsf(clampv(__fmul_rn(c1, vg), vmax)));
-                Vq[(size_t)gr * n + c] = tg;
-            }
+            Attract at;
+            xr = at.xr = Xk[c];
+            at.lr = d.PL[(size_t)k * n + c];
+            at.gr = d.PG[(size_t)g * n + c];
+            at.ax = (float)((at.xr == at.lr) - 1);
+            at.bx = (float)((at.xr == at.gr) - 1);
+            at.bl = (float)(at.lr == at.gr);
+            const float sc = Sp[c];
+            sum = stream_column(rp, rq, c, n, sc, c1, s2, s3, vmax, at, m1, r1, m2, vx);
             Sq[c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
         }
         // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
