@@ -139,11 +139,13 @@ __device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V,
     }
 }
 
-// Per-wave LDS scratch of the selection: dead-row / dead-column flags.
+// Per-wave LDS scratch of the selection: dead-row / dead-column flags and
+// the row claims of a tie group.
 template <int S>
 struct StLds {
     uint8_t deadrow[kMaxN];
     uint8_t deadcol[kMaxN];
+    uint8_t claim[kMaxN];
 };
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -153,15 +155,96 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// A run of selections among the cells holding the current maximum m when
+// every column holds at most one tied Z cell (tz) and at most one tied non-Z
+// cell of known row (tn).  Keys never change and no removal raises one, so
+// the tied set only shrinks, by the chosen column and row, and stays the set
+// of maximal cells until it is empty: each selection i draws the k-th of the
+// T cells left (column-major order, k = bounded(stream word 4 + i, T)), and
+// the run continues without rescans.  Selections are recorded in out and the
+// dead flags (cal cleared for chosen columns; the rest of the per-lane state
+// is brought up to date by st_sync).  Returns the number of selections made.
+template <int CPL, class L>
+__device__ int st_tie_run(int n, int i, StState<CPL>& s, bool (&tz)[CPL], bool (&tn)[CPL], uint8_t* out, L* lds,
+                          uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm)
+{
+    const int l = lane_id();
+    // stream words of 64 blocks ahead, block b0 + l on lane l
+    uint32_t b0 = (4u + (uint32_t)i) >> 2;
+    Philox4 pw = philox4x32_10(b0 + (uint32_t)l, iter, member, swarm, (uint32_t)seed, (uint32_t)(seed >> 32));
+    int taken = 0;
+    for (;;) {
+        int cnt[CPL], incl[CPL], tot[CPL], T = 0;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            cnt[k] = (int)tz[k] + (int)tn[k];
+            incl[k] = wave_incl_scan_i32(cnt[k]);
+            tot[k] = readlane_i32(incl[k], kWave - 1);
+            T += tot[k];
+        }
+        if (T == 0) break;
+        int kk = 0;
+        if (T > 1) {
+            const uint32_t e = 4u + (uint32_t)(i + taken);
+            if ((e >> 2) - b0 >= (uint32_t)kWave) {
+                b0 = e >> 2;
+                pw = philox4x32_10(b0 + (uint32_t)l, iter, member, swarm, (uint32_t)seed, (uint32_t)(seed >> 32));
+            }
+            const int src = (int)((e >> 2) - b0), el = (int)(e & 3u);
+            const uint32_t w = (uint32_t)readlane_i32((int)(el == 0 ? pw.w[0] : el == 1 ? pw.w[1] : el == 2 ? pw.w[2] : pw.w[3]), src);
+            kk = (int)bounded_u32(w, (uint32_t)T);
+        }
+        int c = -1, r = -1;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            if (c >= 0) break;
+            if (kk < tot[k]) {
+                const uint64_t hit = ballot64(cnt[k] > 0 && incl[k] > kk && incl[k] - cnt[k] <= kk);
+                const int owner = __ffsll((long long)hit) - 1;
+                const int within = kk - readlane_i32(incl[k] - cnt[k], owner);
+                const int za = tz[k] ? s.zr[k] : INT_MAX, nb = tn[k] ? s.nzr[k] : INT_MAX;
+                const int lo = min(za, nb), hi = max(za, nb);
+                c = owner + kWave * k;
+                r = readlane_i32(within == 0 ? lo : hi, owner);
+            } else {
+                kk -= tot[k];
+            }
+        }
+        if (c < 0 || c >= n || r < 0 || r >= n) break;  // unreachable when the flags are consistent
+        if (l == 0) {
+            out[c] = (uint8_t)r;
+            lds->deadcol[c] = 1;
+            lds->deadrow[r] = 1;
+        }
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            if (l + kWave * k == c) { s.cal[k] = false; tz[k] = false; tn[k] = false; }
+            if (tz[k] && s.zr[k] == r) tz[k] = false;
+            if (tn[k] && s.nzr[k] == r) tn[k] = false;
+        }
+        ++taken;
+        if (i + taken >= n) break;
+    }
+    return taken;
+}
+
 // One selection by the exact procedure: returns the column (uniform) and
 // sets selr.  A column's candidate is exact unless its cache is stale; a
 // stale cache only bounds the true value from above, so the maximum over all
 // candidates is the true maximum as soon as every column that reaches it is
 // exact.  Only those columns are rescanned (lazy argmax).
-template <int CPL>
+//
+// Tie groups (lds != NULL, Z cells included): when the cells holding the
+// maximum lie in pairwise distinct rows and columns, taking one of them
+// removes none of the others and lowers no key, so the next selections take
+// all of them, whatever the random order; they are taken at once (written to
+// out and the dead flags, cal cleared), *group = their number, and the
+// return value is -1.  The per-lane state other than cal is then stale until
+// st_sync.
+template <int CPL, class L>
 __device__ int st_generic_pick(int n, int i, bool skipZ, const float* __restrict__ V, const float* __restrict__ Vs,
                                StState<CPL>& s, uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm,
-                               int& selr)
+                               int& selr, L* lds = nullptr, uint8_t* out = nullptr, int* group = nullptr)
 {
     const int l = lane_id();
     float cv[CPL], m;
@@ -219,6 +302,49 @@ __device__ int st_generic_pick(int n, int i, bool skipZ, const float* __restrict
                     selr = readlane_i32(cr[k], owner);
                 }
             }
+    }
+    if (selc < 0 && lds) {
+        // a group of single-cell tied columns in distinct rows is taken at once
+        bool multi = false;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) multi |= ballot64(((bal[k] >> l) & 1ull) && cc[k] > 1) != 0;
+        if (!multi) {
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+                if ((bal[k] >> l) & 1ull) lds->claim[cr[k]] = (uint8_t)(l + kWave * k);
+            wave_lds_sync();
+            bool clash = false;
+#pragma unroll
+            for (int k = 0; k < CPL; ++k)
+                clash |= ballot64(((bal[k] >> l) & 1ull) && lds->claim[cr[k]] != (uint8_t)(l + kWave * k)) != 0;
+            if (!clash) {
+#pragma unroll
+                for (int k = 0; k < CPL; ++k)
+                    if ((bal[k] >> l) & 1ull) {
+                        const int c = l + kWave * k;
+                        out[c] = (uint8_t)cr[k];
+                        lds->deadcol[c] = 1;
+                        lds->deadrow[cr[k]] = 1;
+                        s.cal[k] = false;
+                    }
+                *group = ncols;
+                return -1;
+            }
+        }
+        // otherwise a run of selections while the tied set stays of the simple kind
+        bool tz[CPL], tn[CPL], bad = false;
+#pragma unroll
+        for (int k = 0; k < CPL; ++k) {
+            const bool in = (bal[k] >> l) & 1ull;
+            const bool nzt = in && s.nzv[k] == m;
+            tz[k] = in && s.zal[k] && s.zk[k] == m;
+            tn[k] = nzt && s.nzc[k] == 1;
+            bad |= nzt && s.nzc[k] != 1;
+        }
+        if (ballot64(bad) == 0) {
+            *group = st_tie_run<CPL>(n, i, s, tz, tn, out, lds, seed, iter, member, swarm);
+            return -1;
+        }
     }
     if (selc < 0) {
         // |M| tied cells: take the k-th in column-major order
@@ -329,7 +455,7 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
     int i = 0;
     for (; i < depth && i < n; ++i) {
         int selr;
-        const int selc = st_generic_pick<CPL>(n, i, true, V, Vs, s, seed, iter, member, swarm, selr);
+        const int selc = st_generic_pick<CPL, StLds<CPL>>(n, i, true, V, Vs, s, seed, iter, member, swarm, selr);
         if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
         if (l == 0) { out[selc] = (uint8_t)selr; lds->deadcol[selc] = 1; lds->deadrow[selr] = 1; }
         st_apply<CPL>(s, selc, selr);
@@ -355,9 +481,15 @@ __device__ void st_select(int n, int depth, const float* __restrict__ V, const f
         if (i >= n) break;
         wave_lds_sync();
         if (taken) st_sync<CPL>(n, s, lds);
-        // ---- one exact selection
-        int selr;
-        const int selc = st_generic_pick<CPL>(n, i, false, V, Vs, s, seed, iter, member, swarm, selr);
+        // ---- one exact selection, or a row/column-disjoint tie group at once
+        int selr, group = 0;
+        const int selc = st_generic_pick<CPL>(n, i, false, V, Vs, s, seed, iter, member, swarm, selr, lds, out, &group);
+        if (group > 0) {
+            i += group;
+            wave_lds_sync();
+            st_sync<CPL>(n, s, lds);
+            continue;
+        }
         ++i;
         if (selc < 0 || selc >= n || selr < 0 || selr >= n) continue;
         if (l == 0) { out[selc] = (uint8_t)selr; lds->deadcol[selc] = 1; lds->deadrow[selr] = 1; }

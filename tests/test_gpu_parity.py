@@ -210,6 +210,60 @@ def test_secondtarget_with_exact_ties(q, orc, engine, n, depth):
 
 
 @pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("mode", ["disjoint", "clash", "pairs", "pairs2"])
+@pytest.mark.parametrize("n", [40, 128])
+def test_secondtarget_tie_groups(q, orc, engine, mode, n):
+    """Large groups of equal maximal keys.  "disjoint": every column's best
+    non-Z cell (value 0.5) lies on a permutation pi avoiding the rows of X, so
+    after the depth selections the rest of pi is one row/column-disjoint tie
+    group, taken whole.  "clash": pi(c) is the X row of column c + 1, whose Z
+    key 1 - 0.5 ties at 0.5, so the random order decides which cell of each
+    clashing pair survives.  "pairs": the shape of late runs, -0.5 on the X
+    row and +0.5 on a random other row of every column (rows repeat across
+    columns); "pairs2" adds a second +0.5 cell to some columns.  X(t+1) must
+    equal the oracle's SecondTarget."""
+    rng = np.random.default_rng(n + (mode == "clash"))
+    F, D = gen.uniform_instance(n, 0, 20, n)
+    m, S = 1, 8
+    cfg = run_cfg(num_swarms=m, particles_per_swarm=S, norm=False, depth=2, local_search=False, seed=11)
+    announce("tiegroups", engine, mode, n)
+    sw = make_gpu(q, F, D, dict(cfg, engine=engine))
+    st = sw.get_state()
+    V = np.empty((m * S, n, n), np.float32)
+    for k in range(m * S):
+        x = st["X"][k].astype(np.int64)
+        # distinct small values elsewhere (no accidental ties below the maximum)
+        V[k] = (rng.permutation(n * n).reshape(n, n) / (4.0 * n * n) - 0.375).astype(np.float32)
+        cols = np.arange(n)
+        if mode == "disjoint":
+            pi = x[(cols + 1) % n] if n > 1 else x   # a permutation with pi(c) != x(c)
+            V[k][x, cols] = -0.75                    # Z keys 0.25, below the group
+        elif mode == "clash":
+            pi = x[(cols + 1) % n]                   # pi(c) = X row of column c + 1
+            V[k][x, cols] = -0.5                     # Z keys 0.5: each clashes with a pi cell
+        else:
+            pi = (x + rng.integers(1, n, size=n)) % n  # random rows other than X's, with repeats
+            V[k][x, cols] = -0.5
+            if mode == "pairs2":
+                two = rng.random(n) < 0.1
+                r2 = (pi + 1) % n
+                r2 = np.where(r2 == x, (pi + 2) % n, r2)   # neither the X row nor pi
+                V[k][r2[two], cols[two]] = 0.5
+        V[k][pi, cols] = 0.5
+    st["V"] = V
+    sw.set_state(st)
+    sw.step(1)
+    g = sw.get_state()
+    for k in range(m * S):
+        W = orc.keys(V[k].astype(np.float64), st["X"][k])
+        ref, ties = orc.second_target(W, st["X"][k], 2, seed=11, t=st["t"] + 1, particle=k % S, swarm=k // S,
+                                      return_ties=True)
+        assert (ties > 1).sum() > 0
+        assert np.array_equal(g["X"][k], ref), (mode, n, k)
+    sw.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
 def test_norm_run_with_column_scales_n128(q, orc, engine):
     """Norm runs keep V as a matrix times per-column scales; near-equal keys
     1 + v arise often at n = 128.  Ten re-synchronised one-step comparisons."""
