@@ -66,7 +66,15 @@ struct InstDesc {
 };
 
 // ---------------------------------------------------------------- wave ops
-__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+// The lane id goes through an empty asm so that values derived from it are
+// formed where used rather than hoisted out of a long loop (where they would
+// hold vector registers for its whole length).
+__device__ __forceinline__ int lane_id()
+{
+    int l = (int)__lane_id();
+    asm volatile("" : "+v"(l));
+    return l;
+}
 
 template <int CTRL, int ROW_MASK = 0xF>
 __device__ __forceinline__ float dpp_f32(float v)
@@ -87,10 +95,37 @@ __device__ __forceinline__ float wave_max(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// DPP move of a 32-bit value; lanes whose row is masked off, or whose source lies
+// outside the row, receive `old`.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ int dpp_i32(int old, int v)
+{
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Sum over the 64 lanes, returned to every lane (uniform).  Same row steps as
+// wave_max, with 0 entering from masked rows.
 __device__ __forceinline__ int wave_sum_i32(int v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    v += dpp_i32<0xB1>(0, v);
+    v += dpp_i32<0x4E>(0, v);
+    v += dpp_i32<0x141>(0, v);
+    v += dpp_i32<0x140>(0, v);
+    v += dpp_i32<0x142, 0xA>(0, v);
+    v += dpp_i32<0x143, 0xC>(0, v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Inclusive prefix sum over the lanes in lane order: row_shr 1, 2, 4, 8 inside
+// each row of 16, then the row totals by row_bcast15 / row_bcast31.
+__device__ __forceinline__ int wave_incl_scan_i32(int v)
+{
+    v += dpp_i32<0x111>(0, v);
+    v += dpp_i32<0x112>(0, v);
+    v += dpp_i32<0x114>(0, v);
+    v += dpp_i32<0x118>(0, v);
+    v += dpp_i32<0x142, 0xA>(0, v);
+    v += dpp_i32<0x143, 0xC>(0, v);
     return v;
 }
 
@@ -101,15 +136,26 @@ __device__ __forceinline__ long long wave_sum_i64(long long v)
     return v;
 }
 
-__device__ __forceinline__ int wave_incl_scan_i32(int v)
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ long long dpp_i64(long long v)
 {
-    const int l = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(v, off, kWave);
-        if (l >= off) v += u;
-    }
-    return v;
+    const int lo = dpp_i32<CTRL, ROW_MASK>((int)v, (int)v);
+    const int hi = dpp_i32<CTRL, ROW_MASK>((int)(v >> 32), (int)(v >> 32));
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Minimum over the 64 lanes, returned to every lane (uniform).
+__device__ __forceinline__ long long wave_min_i64(long long v)
+{
+    long long o;
+    o = dpp_i64<0xB1>(v); v = o < v ? o : v;
+    o = dpp_i64<0x4E>(v); v = o < v ? o : v;
+    o = dpp_i64<0x141>(v); v = o < v ? o : v;
+    o = dpp_i64<0x140>(v); v = o < v ? o : v;
+    o = dpp_i64<0x142, 0xA>(v); v = o < v ? o : v;
+    o = dpp_i64<0x143, 0xC>(v); v = o < v ? o : v;
+    const int lo = __builtin_amdgcn_readlane((int)v, 63), hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 
 __device__ __forceinline__ int readlane_i32(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
