@@ -128,8 +128,18 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
                          qap_swarm** out);
 
 /* Enqueue `iterations` >= 0 iterations on the handle's stream and return
- * without waiting.  Device errors surface here or on a later call. */
+ * without waiting.  Device errors surface here or on a later call.  One
+ * iteration of all instances of a handle is one launch per fused-kernel class
+ * (instances with the same padded size and symmetry share a launch), the
+ * per-stage kernels of instances outside the int8 path, and one batched
+ * launch each for the swarm bests and the finish step.  The first call
+ * captures that sequence into a HIP graph, which every iteration then
+ * replays; a stream that cannot be captured keeps eager launches. */
 int qap_swarm_step(qap_swarm* h, int32_t iterations);
+
+/* *active = 1 if qap_swarm_step replays a captured graph (0: eager launches,
+ * before the first step, or while profiling). */
+int qap_swarm_graph(qap_swarm* h, int32_t* active);
 
 /* Wait for the handle's stream. */
 int qap_swarm_sync(qap_swarm* h);

@@ -30,7 +30,7 @@ QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
 
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
-           "qap_swarm_path", "qap_swarm_profile", "qap_swarm_destroy", "qap_swarm_strerror"]
+           "qap_swarm_path", "qap_swarm_graph", "qap_swarm_profile", "qap_swarm_destroy", "qap_swarm_strerror"]
 STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
@@ -81,6 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_eval.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int64),
                                  P(ctypes.c_int64)]
     L.qap_swarm_path.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
+    L.qap_swarm_graph.argtypes = [vp, P(ctypes.c_int32)]
     L.qap_swarm_profile.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     L.qap_swarm_destroy.argtypes = [vp]
     L.qap_swarm_destroy.restype = None
@@ -270,6 +271,12 @@ class Swarm:
         s = ctypes.c_int32()
         _check(load_library().qap_swarm_path(self.h, instance, ctypes.byref(p), ctypes.byref(s)), "qap_swarm_path")
         return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32"}[p.value], bool(s.value)
+
+    def graph_active(self) -> bool:
+        """Whether stepping replays a captured HIP graph."""
+        a = ctypes.c_int32()
+        _check(load_library().qap_swarm_graph(self.h, ctypes.byref(a)), "qap_swarm_graph")
+        return bool(a.value)
 
     def profile(self, enable: bool):
         """Switch profiled stepping on/off; returns ({stage: ms}, iterations) so far."""

@@ -61,6 +61,7 @@ struct InstDesc {
     SwarmMin* smin;         // [m]
     BestRec* best;          // [1]
     int* iter;              // [1] completed iterations
+    int* order;             // [m] migration ranking scratch
     uint8_t* Xnew;          // [P][n] SecondTarget output (per-stage engine)
     int* scratch;           // per-block contraction scratch (per-stage engine)
 };

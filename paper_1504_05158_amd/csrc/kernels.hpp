@@ -8,23 +8,33 @@ namespace qap {
 // Initialisation (iteration 0) of one instance.
 hipError_t launch_init(const InstDesc& d, hipStream_t st);
 
-// Per-stage engine: one iteration of one instance (S_x, velocity,
-// goal + deltas + local search, swarm bests, finish).  If ev is not NULL,
-// events are recorded around the stages: ev[2s], ev[2s+1] for stage s
-// (0 S_x, 1 velocity, 2 goal/deltas, 4 bests).
-hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st,
-                             hipEvent_t* ev);
+// Per-stage engine: the stage kernels of one iteration of one instance (S_x,
+// velocity, goal + deltas + local search); the bests follow, batched over the
+// handle (launch_bests).  If ev is not NULL, events are recorded around the
+// stages: ev[2s], ev[2s+1] for stage s (0 S_x, 1 velocity, 2 goal/deltas).
+hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, hipStream_t st, hipEvent_t* ev);
 
 // Goal (+ deltas) of `count` permutations [count][n] (device) on the int32 path.
 // mode 1: eval into goals/deltas; mode 2: initial goals of the particles.
 hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, const uint8_t* perms, int count,
                                  int mode, long long* goals, long long* deltas, hipStream_t st);
 
-// Swarm bests + finish (best-ever, migration, iteration counter).
-hipError_t launch_bests(const InstDesc& d, int init, int* order, hipStream_t st);
+// Swarm bests + finish (best-ever, migration, iteration counter) of every
+// instance of a handle: descs [count] device descriptors, smap [total_swarms]
+// device map workgroup -> (instance, swarm).
+hipError_t launch_bests(const InstDesc* descs, const int2* smap, int total_swarms, int count, int init,
+                        hipStream_t st);
 
-// Fused engine: one iteration of one instance in one kernel, plus bests.
-hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipEvent_t* ev);
+// Fused engine: one iteration of every instance of one kernel class (npad,
+// symmetric, zero diagonals) in one launch.  A class of one instance passes its
+// host descriptor `one` (a kernel argument); otherwise one = NULL and descs
+// [instances of the class] and blkmap [blocks] (workgroup -> (class-local
+// instance, first particle)) are device tables.  Bests follow separately.
+hipError_t launch_fused_class(int npad, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
+                              const int2* blkmap, int blocks, hipStream_t st);
+
+// Particles per workgroup of the fused kernel.
+constexpr int kFusedParticlesPerBlock = 4;
 
 // Whether the fused kernel covers an instance (int8 path, n <= 160).
 bool fused_supported(const InstDesc& d);

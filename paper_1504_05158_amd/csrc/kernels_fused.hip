@@ -364,9 +364,16 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
 }  // namespace
 
 // ------------------------------------------------------------------ fused step
-template <int NP, bool SYM, bool ZD>
-__global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
+// TABLE: workgroup b steps particles blkmap[b].y .. +3 of instance
+// descs[blkmap[b].x]; otherwise workgroup b steps particles 4b .. 4b+3 of the
+// instance passed as `one` (a kernel argument, whose pointers the compiler
+// knows to be global: accesses through them avoid flat instructions).
+template <int NP, bool SYM, bool ZD, bool TABLE>
+__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
+                                                    const int2* __restrict__ blkmap)
 {
+    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
+    const InstDesc& d = TABLE ? descs[bm.x] : one;
     constexpr int CPL = NP <= 64 ? 1 : NP <= 128 ? 2 : 4;  // column slots per lane
     __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
@@ -380,7 +387,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc d)
 
     // wave index made explicitly uniform: every per-particle address lives in scalar registers
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), l = lane_id();
-    const int k = blockIdx.x * kWaves + w;
+    const int k = bm.y + w;
     if (k >= d.P) return;
     const int n = d.n;
     const int tprev = *d.iter;
@@ -505,42 +512,41 @@ __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __
 // Contraction variants: general (F or D not symmetric), symmetric, symmetric
 // with zero diagonals.
 template <int NP, bool SYM, bool ZD>
-static hipError_t fused_launch_one(const InstDesc& d, hipStream_t st)
+static hipError_t fused_launch_one(const InstDesc* one, const InstDesc* descs, const int2* blkmap, int blocks,
+                                   hipStream_t st)
 {
-    const dim3 grid((unsigned)((d.P + kWaves - 1) / kWaves)), block(kWaves * kWave);
-    hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD>), grid, block, 0, st, d);
+    const dim3 grid((unsigned)blocks), block(kWaves * kWave);
+    if (one)
+        hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, false>), grid, block, 0, st, *one, descs, blkmap);
+    else
+        hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
     return hipGetLastError();
 }
 
 template <bool SYM, bool ZD>
-static hipError_t fused_launch_np(const InstDesc& d, hipStream_t st)
+static hipError_t fused_launch_np(int npad, const InstDesc* one, const InstDesc* descs, const int2* blkmap,
+                                  int blocks, hipStream_t st)
 {
-    switch (d.npad) {
-    case 32: return fused_launch_one<32, SYM, ZD>(d, st);
-    case 64: return fused_launch_one<64, SYM, ZD>(d, st);
-    case 96: return fused_launch_one<96, SYM, ZD>(d, st);
-    case 128: return fused_launch_one<128, SYM, ZD>(d, st);
-    case 160: return fused_launch_one<160, SYM, ZD>(d, st);
+    switch (npad) {
+    case 32: return fused_launch_one<32, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 64: return fused_launch_one<64, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 96: return fused_launch_one<96, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 128: return fused_launch_one<128, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 160: return fused_launch_one<160, SYM, ZD>(one, descs, blkmap, blocks, st);
     default: return hipErrorNotSupported;
     }
 }
 
-
 bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160; }
 
-hipError_t launch_fused_step(const InstDesc& d, int* order, hipStream_t st, hipEvent_t* ev)
+hipError_t launch_fused_class(int npad, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
+                              const int2* blkmap, int blocks, hipStream_t st)
 {
-    hipError_t e;
-    if (ev && (e = hipEventRecord(ev[6], st)) != hipSuccess) return e;
-    e = !d.sym ? fused_launch_np<false, false>(d, st)
-               : d.zd ? fused_launch_np<true, true>(d, st) : fused_launch_np<true, false>(d, st);
-    if (e != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[7], st)) != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[8], st)) != hipSuccess) return e;
-    e = launch_bests(d, 0, order, st);
-    if (e != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[9], st)) != hipSuccess) return e;
-    return hipSuccess;
+    static_assert(kWaves == kFusedParticlesPerBlock, "one wave per particle");
+    if (blocks <= 0) return hipSuccess;
+    return !sym ? fused_launch_np<false, false>(npad, one, descs, blkmap, blocks, st)
+                : zd ? fused_launch_np<true, true>(npad, one, descs, blkmap, blocks, st)
+                     : fused_launch_np<true, false>(npad, one, descs, blkmap, blocks, st);
 }
 
 template <bool SYM, bool ZD>

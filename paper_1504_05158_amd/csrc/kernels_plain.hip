@@ -307,14 +307,18 @@ template __global__ void k_goal_delta_i32<true, false>(InstDesc, const uint8_t*,
 template __global__ void k_goal_delta_i32<true, true>(InstDesc, const uint8_t*, int, int, long long*, long long*);
 
 // ------------------------------------------------------------------ swarm best
-// One workgroup per swarm: the best member of this iteration (lowest index on
+// One workgroup per swarm of any instance of the handle (smap: workgroup ->
+// (instance, swarm)): the best member of this iteration (lowest index on
 // ties); P^G <- its current solution on strict improvement (Sec. 3.2 P^G[k]).
 // init != 0: iteration 0 (solutions in buffer 0).
-__global__ __launch_bounds__(256) void k_swarm_best(InstDesc d, int init)
+__global__ __launch_bounds__(256) void k_swarm_best(const InstDesc* __restrict__ descs, const int2* __restrict__ smap,
+                                                    int init)
 {
     __shared__ long long sg[4];
     __shared__ int sm[4];
-    const int g = blockIdx.x, tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+    const int2 ig = smap[blockIdx.x];
+    const InstDesc& d = descs[ig.x];
+    const int g = ig.y, tid = threadIdx.x, l = tid & 63, w = tid >> 6;
     const int n = d.n, S = d.S;
     const int nxt = init ? 0 : ((*d.iter & 1) ^ 1);
     long long bg = LLONG_MAX;
@@ -347,12 +351,14 @@ __global__ __launch_bounds__(256) void k_swarm_best(InstDesc d, int init)
 }
 
 // ------------------------------------------------------------------ finish
-// One workgroup per instance: best-ever record, migration (Alg. 2) when due,
-// and the iteration counter.  Swarms are ranked by (goal of P^G, index);
-// for k < d a uniformly drawn member of the k-th best swarm gives its current
-// solution and goal to the k-th worst swarm.
-__global__ __launch_bounds__(256) void k_finish(InstDesc d, int init, int* __restrict__ order)
+// One workgroup per instance (descs[blockIdx.x]): best-ever record, migration
+// (Alg. 2) when due, and the iteration counter.  Swarms are ranked by (goal of
+// P^G, index); for k < d a uniformly drawn member of the k-th best swarm gives
+// its current solution and goal to the k-th worst swarm.
+__global__ __launch_bounds__(256) void k_finish(const InstDesc* __restrict__ descs, int init)
 {
+    const InstDesc& d = descs[blockIdx.x];
+    int* __restrict__ order = d.order;
     __shared__ long long sg[4];
     __shared__ int ss[4];
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
@@ -438,12 +444,13 @@ hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, cons
     return hipGetLastError();
 }
 
-hipError_t launch_bests(const InstDesc& d, int init, int* order, hipStream_t st)
+hipError_t launch_bests(const InstDesc* descs, const int2* smap, int total_swarms, int count, int init,
+                        hipStream_t st)
 {
-    hipLaunchKernelGGL(k_swarm_best, dim3(d.m), dim3(256), 0, st, d, init);
+    hipLaunchKernelGGL(k_swarm_best, dim3((unsigned)total_swarms), dim3(256), 0, st, descs, smap, init);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, d, init, order);
+    hipLaunchKernelGGL(k_finish, dim3((unsigned)count), dim3(256), 0, st, descs, init);
     return hipGetLastError();
 }
 
@@ -456,8 +463,7 @@ hipError_t launch_init(const InstDesc& d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* order, hipStream_t st,
-                             hipEvent_t* ev)
+hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, hipStream_t st, hipEvent_t* ev)
 {
     const int cpl = d.n <= 64 ? 1 : d.n <= 128 ? 2 : 4;
     const dim3 gst(blocks_for(d.P, 4)), bst(256);
@@ -481,10 +487,6 @@ hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, int* ord
     e = launch_goal_delta_i32(d, mul24, grid_gd, d.Xnew, d.P, 0, nullptr, nullptr, st);
     if (e != hipSuccess) return e;
     REC(5);
-    REC(8);
-    e = launch_bests(d, 0, order, st);
-    if (e != hipSuccess) return e;
-    REC(9);
 #undef REC
     return hipSuccess;
 }

@@ -26,21 +26,44 @@ struct Instance {
     std::vector<void*> allocs;
 };
 
+// Device tables of one step over all instances of a handle: every descriptor,
+// the swarm map of the batched bests, and per fused-kernel class (npad,
+// symmetric, zero diagonals) its descriptors and workgroup map.
+struct FusedClass {
+    int npad = 0;
+    bool sym = false, zd = false;
+    int blocks = 0;
+    qap::InstDesc* descs = nullptr;  // device [instances of the class]
+    int2* blkmap = nullptr;          // device [blocks]: (class-local instance, first particle)
+    std::vector<qap::InstDesc> host; // the class's descriptors (one instance: passed by value)
+};
+
+struct StepPlan {
+    qap::InstDesc* descs = nullptr;  // device [instances]
+    int2* smap = nullptr;            // device [total swarms]: (instance, swarm)
+    int total_swarms = 0;
+    std::vector<FusedClass> fused;
+    std::vector<int> plain;          // instances stepped by the per-stage kernels
+    std::vector<void*> allocs;
+};
+
 }  // namespace
 
 struct qap_swarm {
     std::vector<Instance> inst;
+    StepPlan plan;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int engine = QAP_ENGINE_PLAIN;
     int sticky = QAP_OK;
     int grid_gd = 0;
     int device = 0;
-    hipGraphExec_t graph = nullptr;
-    bool graph_ready = false;
+    hipGraphExec_t graph = nullptr;  // one iteration, captured at the first step
+    bool graph_failed = false;       // capture unavailable on this stream: eager launches
     // profiled stepping
     bool profiling = false;
-    std::vector<hipEvent_t> ev_pool;   // 2 * QAP_NUM_STAGES per recorded iteration
+    std::vector<hipEvent_t> ev_pool;   // sets of 2 * QAP_NUM_STAGES events
+    std::vector<uint8_t> ev_mask;      // per set: stages recorded since the set was handed out
     size_t ev_used = 0;
     double stage_ms[QAP_NUM_STAGES] = {};
     long long prof_iters = 0;
@@ -205,6 +228,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     TRY(dalloc(I, &d.best, 1));
     TRY(dalloc(I, &d.iter, 1));
     TRY(dalloc(I, &I.order, (size_t)I.m));
+    d.order = I.order;
     TRY(dalloc(I, &d.scratch, (size_t)h->grid_gd * nn * (sym ? 1 : 2)));
     // iteration 0
     std::vector<long long> big((size_t)I.m, LLONG_MAX);
@@ -217,27 +241,108 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     TRY(hipMemcpy(d.iter, &zero, sizeof zero, hipMemcpyHostToDevice));
     TRY(qap::launch_init(d, h->stream));
     TRY(qap::launch_goal_delta_i32(d, mul24, h->grid_gd, d.X[0], I.P, 2, nullptr, nullptr, h->stream));
-    TRY(qap::launch_bests(d, 1, I.order, h->stream));
-    TRY(hipStreamSynchronize(h->stream));
 #undef TRY
+    return QAP_OK;
+}
+
+template <class T>
+hipError_t plan_upload(StepPlan& pl, T** p, const std::vector<T>& v)
+{
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, v.size() * sizeof(T) > 0 ? v.size() * sizeof(T) : 1);
+    if (e != hipSuccess) return e;
+    pl.allocs.push_back(q);
+    *p = static_cast<T*>(q);
+    if (v.empty()) return hipSuccess;
+    return hipMemcpy(q, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_plan(StepPlan& pl)
+{
+    for (void* p : pl.allocs) (void)hipFree(p);
+    pl = StepPlan();
+}
+
+// The step's device tables (after every instance is set up).
+int build_plan(qap_swarm* h)
+{
+    StepPlan& pl = h->plan;
+    const int count = (int)h->inst.size();
+    std::vector<qap::InstDesc> all((size_t)count);
+    std::vector<int2> smap;
+    for (int k = 0; k < count; ++k) {
+        all[(size_t)k] = h->inst[(size_t)k].d;
+        for (int g = 0; g < h->inst[(size_t)k].m; ++g) smap.push_back(make_int2(k, g));
+    }
+    pl.total_swarms = (int)smap.size();
+    hipError_t e = plan_upload(pl, &pl.descs, all);
+    if (e == hipSuccess) e = plan_upload(pl, &pl.smap, smap);
+    if (e != hipSuccess) return dev_err(nullptr, e);
+    // fused classes, larger matrices first
+    std::vector<std::vector<int>> members;
+    for (int k = 0; k < count; ++k) {
+        const qap::InstDesc& d = all[(size_t)k];
+        if (h->engine != QAP_ENGINE_FUSED || !qap::fused_supported(d)) {
+            pl.plain.push_back(k);
+            continue;
+        }
+        size_t c = 0;
+        while (c < pl.fused.size() &&
+               !(pl.fused[c].npad == d.npad && pl.fused[c].sym == (d.sym != 0) && pl.fused[c].zd == (d.zd != 0)))
+            ++c;
+        if (c == pl.fused.size()) {
+            FusedClass fc;
+            fc.npad = d.npad;
+            fc.sym = d.sym != 0;
+            fc.zd = d.zd != 0;
+            pl.fused.push_back(fc);
+            members.emplace_back();
+        }
+        members[c].push_back(k);
+    }
+    for (size_t c = 0; c < pl.fused.size(); ++c) {
+        FusedClass& fc = pl.fused[c];
+        std::vector<qap::InstDesc> descs;
+        std::vector<int2> blkmap;
+        for (int k : members[c]) {
+            const int j = (int)descs.size();
+            descs.push_back(all[(size_t)k]);
+            for (int first = 0; first < all[(size_t)k].P; first += qap::kFusedParticlesPerBlock)
+                blkmap.push_back(make_int2(j, first));
+        }
+        fc.blocks = (int)blkmap.size();
+        fc.host = descs;
+        e = plan_upload(pl, &fc.descs, descs);
+        if (e == hipSuccess) e = plan_upload(pl, &fc.blkmap, blkmap);
+        if (e != hipSuccess) return dev_err(nullptr, e);
+    }
+    std::stable_sort(pl.fused.begin(), pl.fused.end(),
+                     [](const FusedClass& a, const FusedClass& b) { return a.npad > b.npad; });
     return QAP_OK;
 }
 
 constexpr int kEvPerIter = 2 * QAP_NUM_STAGES;
 
-hipEvent_t* prof_events(qap_swarm* h)
+// A fresh set of events (ev[2s], ev[2s+1] bracket stage s, see ev_set): its
+// index, or -1 if events cannot be created.  Growing the pool may move it, so
+// callers keep indices, not pointers, across calls.
+long prof_events(qap_swarm* h)
 {
     if (h->ev_used + kEvPerIter > h->ev_pool.size()) {
         for (int i = 0; i < kEvPerIter; ++i) {
             hipEvent_t e;
-            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            if (hipEventCreate(&e) != hipSuccess) return -1;
             h->ev_pool.push_back(e);
         }
+        h->ev_mask.push_back(0);
     }
-    hipEvent_t* ev = h->ev_pool.data() + h->ev_used;
+    const long set = (long)(h->ev_used / kEvPerIter);
+    h->ev_mask[(size_t)set] = 0;
     h->ev_used += kEvPerIter;
-    return ev;
+    return set;
 }
+
+hipEvent_t* ev_set(qap_swarm* h, long set) { return h->ev_pool.data() + (size_t)set * kEvPerIter; }
 
 // Fold the recorded event pairs into the per-stage totals.
 int prof_collect(qap_swarm* h)
@@ -245,38 +350,96 @@ int prof_collect(qap_swarm* h)
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return dev_err(h, e);
     for (size_t base = 0; base + kEvPerIter <= h->ev_used; base += kEvPerIter) {
+        const uint8_t mask = h->ev_mask[base / kEvPerIter];
         for (int s = 0; s < QAP_NUM_STAGES; ++s) {
             float ms = 0.0f;
-            if (hipEventElapsedTime(&ms, h->ev_pool[base + 2 * s], h->ev_pool[base + 2 * s + 1]) == hipSuccess)
+            if (((mask >> s) & 1) &&
+                hipEventElapsedTime(&ms, h->ev_pool[base + 2 * s], h->ev_pool[base + 2 * s + 1]) == hipSuccess)
                 h->stage_ms[s] += ms;
         }
     }
-    (void)hipGetLastError();  // stages an engine does not record leave unrecorded pairs
+    (void)hipGetLastError();
     h->ev_used = 0;
     return QAP_OK;
 }
 
+// One iteration of every instance, launched one by one: the fused classes, the
+// per-stage instances, then the batched bests.  With profiling on, events
+// bracket the stages.
 int enqueue_iteration(qap_swarm* h)
 {
-    for (Instance& I : h->inst) {
-        hipError_t e;
-        hipEvent_t* ev = nullptr;
-        if (h->profiling) {
-            if (h->ev_used + kEvPerIter > 4096) {
-                const int rc = prof_collect(h);
-                if (rc != QAP_OK) return rc;
-            }
-            ev = prof_events(h);
-            if (!ev) return dev_err(h, hipErrorOutOfMemory);
+    const StepPlan& pl = h->plan;
+    hipError_t e = hipSuccess;
+    long set = -1;
+    if (h->profiling) {
+        if (h->ev_used + kEvPerIter * (1 + pl.plain.size()) > 4096) {
+            const int rc = prof_collect(h);
+            if (rc != QAP_OK) return rc;
         }
-        if (h->engine == QAP_ENGINE_FUSED && qap::fused_supported(I.d))
-            e = qap::launch_fused_step(I.d, I.order, h->stream, ev);
-        else  // per-stage kernels: the plain engine, and the int32 range fallback of the fused one
-            e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, I.order, h->stream, ev);
-        if (e != hipSuccess) return dev_err(h, e);
+        set = prof_events(h);
+        if (set < 0) return dev_err(h, hipErrorOutOfMemory);
     }
+#define REC(i)                                                                                          \
+    do {                                                                                                \
+        if (set >= 0 && (e = hipEventRecord(ev_set(h, set)[i], h->stream)) != hipSuccess) return dev_err(h, e); \
+    } while (0)
+    if (!pl.fused.empty()) {
+        REC(2 * QAP_STAGE_FUSED);
+        for (const FusedClass& fc : pl.fused) {
+            e = qap::launch_fused_class(fc.npad, fc.sym, fc.zd, fc.host.size() == 1 ? &fc.host[0] : nullptr,
+                                        fc.descs, fc.blkmap, fc.blocks, h->stream);
+            if (e != hipSuccess) return dev_err(h, e);
+        }
+        REC(2 * QAP_STAGE_FUSED + 1);
+        if (set >= 0) h->ev_mask[(size_t)set] |= 1u << QAP_STAGE_FUSED;
+    }
+    for (size_t j = 0; j < pl.plain.size(); ++j) {
+        const Instance& I = h->inst[(size_t)pl.plain[j]];
+        long setp = -1;
+        if (h->profiling) {
+            setp = prof_events(h);
+            if (setp < 0) return dev_err(h, hipErrorOutOfMemory);
+        }
+        e = qap::launch_plain_step(I.d, I.mul24, h->grid_gd, h->stream, setp >= 0 ? ev_set(h, setp) : nullptr);
+        if (e != hipSuccess) return dev_err(h, e);
+        if (setp >= 0)
+            h->ev_mask[(size_t)setp] |= (1u << QAP_STAGE_SX) | (1u << QAP_STAGE_VELOCITY) | (1u << QAP_STAGE_GOAL_DELTA);
+    }
+    REC(2 * QAP_STAGE_BESTS);
+    e = qap::launch_bests(pl.descs, pl.smap, pl.total_swarms, (int)h->inst.size(), 0, h->stream);
+    if (e != hipSuccess) return dev_err(h, e);
+    REC(2 * QAP_STAGE_BESTS + 1);
+    if (set >= 0) h->ev_mask[(size_t)set] |= 1u << QAP_STAGE_BESTS;
+#undef REC
     if (h->profiling) h->prof_iters += 1;
     return QAP_OK;
+}
+
+// Capture one iteration into a graph (replayed once per iteration).  A stream
+// that cannot be captured leaves the handle on eager launches.
+void capture_iteration(qap_swarm* h)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph_failed = true;
+        return;
+    }
+    const int rc = enqueue_iteration(h);
+    const hipError_t e = hipStreamEndCapture(h->stream, &g);
+    if (rc != QAP_OK || e != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        if (rc != QAP_OK) h->sticky = QAP_OK;  // nothing ran: the capture only recorded
+        h->graph_failed = true;
+        return;
+    }
+    if (hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        h->graph = nullptr;
+        h->graph_failed = true;
+    }
+    (void)hipGraphDestroy(g);
 }
 
 int get_instance(qap_swarm* h, int32_t k, Instance** out)
@@ -311,6 +474,7 @@ void qap_swarm_destroy(qap_swarm* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    free_plan(h->plan);
     for (Instance& I : h->inst) free_instance(I);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -350,6 +514,13 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
                                       mul24[(size_t)k], zd[(size_t)k]);
         if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
     }
+    int rc = build_plan(h);
+    if (rc == QAP_OK) {
+        hipError_t e = qap::launch_bests(h->plan.descs, h->plan.smap, h->plan.total_swarms, count, 1, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        rc = dev_err(nullptr, e);
+    }
+    if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
     *out = h;
     return QAP_OK;
 }
@@ -364,6 +535,12 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations)
     if (!h || iterations < 0) return QAP_ERR_INVALID_ARG;
     if (h->sticky != QAP_OK) return h->sticky;
     for (int it = 0; it < iterations; ++it) {
+        if (!h->profiling && !h->graph && !h->graph_failed) capture_iteration(h);
+        if (!h->profiling && h->graph) {
+            const hipError_t e = hipGraphLaunch(h->graph, h->stream);
+            if (e != hipSuccess) return dev_err(h, e);
+            continue;
+        }
         const int rc = enqueue_iteration(h);
         if (rc != QAP_OK) return rc;
     }
@@ -569,6 +746,13 @@ int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* l
         for (double& v : h->stage_ms) v = 0.0;
         h->prof_iters = 0;
     }
+    return QAP_OK;
+}
+
+int qap_swarm_graph(qap_swarm* h, int32_t* active)
+{
+    if (!h || !active) return QAP_ERR_INVALID_ARG;
+    *active = (h->graph && !h->profiling) ? 1 : 0;
     return QAP_OK;
 }
 

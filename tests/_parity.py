@@ -1,4 +1,6 @@
 """Helpers shared by the GPU parity tests (GPU library vs CPU oracle)."""
+import sys
+
 import numpy as np
 
 VTOL = 1e-5  # FP32 velocities vs the FP64 oracle, relative to each column's largest entry
@@ -50,3 +52,9 @@ def assert_states_equal(g, o, vtol=VTOL, what=""):
     assert list(np.asarray(g["best_info"])) == list(np.asarray(o["best_info"])), (what, g["best_info"], o["best_info"])
     assert int(g["t"]) == int(o["t"])
     assert_v_close(g["V"], o["V"], vtol)
+
+
+def announce(*a):
+    """Name the GPU case on stdout before it runs (a fault then points at it)."""
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()

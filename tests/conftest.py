@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def q():
+    """The HIP library's Python binding (GPU tests only)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1504_05158_amd as q
+    q.load_library()
+    return q

@@ -11,26 +11,11 @@ import numpy as np
 import pytest
 
 import qap_inputs as gen
-from _parity import assert_states_equal, assert_v_close, make_gpu, oracle_from_state, run_cfg
+from _parity import announce, assert_states_equal, assert_v_close, make_gpu, oracle_from_state, run_cfg
 
 pytestmark = pytest.mark.gpu
 
 ENGINES = ["fused", "plain"]
-
-
-@pytest.fixture(scope="module")
-def q():
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    import paper_1504_05158_amd as q
-    q.load_library()
-    return q
-
-
-def announce(*a):
-    print("[case]", *a, flush=True)
-    sys.stdout.flush()
 
 
 INSTANCES = [
