@@ -69,9 +69,11 @@ typedef struct {
  *    floor(migration_factor * m), which must be < m/2; the period is >= 1.
  *  local_search: 1 = one best-improvement pair exchange per particle-iteration.
  *  delta_path: contraction used for the pair-exchange deltas (AUTO picks int8
- *    MFMA when every F, D entry is in [-128, 127]).
- *  engine: QAP_ENGINE_FUSED (one kernel per step, replayed from a HIP graph) or
- *    QAP_ENGINE_PLAIN (one kernel per stage, int32 contraction).
+ *    MFMA when every F, D entry is in [-128, 127] and n <= 160; INT8_MFMA with
+ *    n > 160 also runs on the int32 path, which qap_swarm_path reports).
+ *  engine: QAP_ENGINE_FUSED (one kernel per step for int8 instances, per-stage
+ *    kernels otherwise; steps replay a HIP graph) or QAP_ENGINE_PLAIN (one
+ *    kernel per stage, int32 contraction).
  *  seed: key of the random stream.  stream: hipStream_t to run on (NULL = the
  *    library's own stream). */
 typedef struct {

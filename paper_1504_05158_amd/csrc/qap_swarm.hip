@@ -147,7 +147,7 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
     } else {
         pth = f8 ? 1 : 2;
     }
-    if (engine == QAP_ENGINE_PLAIN) pth = 2;
+    if (engine == QAP_ENGINE_PLAIN || n > 160) pth = 2;  // the fused kernel covers n <= 160
     *path = pth;
     *sym = s ? 1 : 0;
     *mul24 = (mf < (1LL << 23) && md < (1LL << 23)) ? 1 : 0;

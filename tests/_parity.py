@@ -58,3 +58,31 @@ def announce(*a):
     """Name the GPU case on stdout before it runs (a fault then points at it)."""
     print("[case]", *a, flush=True)
     sys.stdout.flush()
+
+
+def oracle_particle_step(orc, F, D, cfg, st, k):
+    """One iteration t -> t+1 of particle k alone, from an exported state st,
+    by the oracle's per-particle functions (velocity, keys, SecondTarget, local
+    search, goal), in the order of the oracle's swarm step.  Returns the
+    particle's V, X, goal, P^L and goal of P^L after the iteration (P^G and the
+    bests need the whole swarm and are not produced)."""
+    S = cfg["particles_per_swarm"]
+    g, s = divmod(int(k), S)
+    t1 = int(st["t"]) + 1
+    seed = cfg["seed"]
+    r2 = orc.u01(orc.word(seed, 0, t1, s, g))
+    r3 = orc.u01(orc.word(seed, 1, t1, s, g))
+    V = np.asarray(st["V"][k], np.float64)
+    x = np.asarray(st["X"][k])
+    Vn = orc.velocity(V, x, st["PL"][k], st["PG"][g], cfg["c1"], cfg["c2"], cfg["c3"], r2, r3, cfg["vmax"],
+                      cfg["norm"])
+    xs = orc.second_target(orc.keys(V, x), x, cfg["depth"], seed=seed, t=t1, particle=s, swarm=g)
+    if cfg["local_search"]:
+        xs, goal, _, _ = orc.local_search(F, D, xs)
+    else:
+        goal = orc.cost(F, D, xs)
+    if goal < int(st["goalPL"][k]):
+        pl, gpl = xs.copy(), goal
+    else:
+        pl, gpl = np.asarray(st["PL"][k]).copy(), int(st["goalPL"][k])
+    return Vn, np.asarray(xs), int(goal), np.asarray(pl), int(gpl)
