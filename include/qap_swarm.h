@@ -75,7 +75,10 @@ typedef struct {
  *    kernels otherwise; steps replay a HIP graph) or QAP_ENGINE_PLAIN (one
  *    kernel per stage, int32 contraction).
  *  seed: key of the random stream.  stream: hipStream_t to run on (NULL = the
- *    library's own stream). */
+ *    library's own stream).
+ *  stream_groups: 0 = automatic (independent swarms on the fused kernel are
+ *    stepped as up to 3 concurrent groups of swarms, see qap_swarm_step), or 1-3
+ *    to set the number of groups (results are the same for every choice). */
 typedef struct {
     int32_t num_swarms;
     int32_t particles_per_swarm;
@@ -91,6 +94,7 @@ typedef struct {
     int32_t engine;
     uint64_t seed;
     void* stream;
+    int32_t stream_groups;
 } qap_params;
 
 /* Host-side copy of one instance's state (checkpoint / inspection).  Every
@@ -130,18 +134,24 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
                          qap_swarm** out);
 
 /* Enqueue `iterations` >= 0 iterations on the handle's stream and return
- * without waiting.  Device errors surface here or on a later call.  One
- * iteration of all instances of a handle is one launch per fused-kernel class
- * (instances with the same padded size and symmetry share a launch), the
- * per-stage kernels of instances outside the int8 path, and one batched
- * launch each for the swarm bests and the finish step.  The first call
- * captures that sequence into a HIP graph, which every iteration then
- * replays; a stream that cannot be captured keeps eager launches. */
+ * without waiting.  Device errors surface here or on a later call.
+ * Independent swarms on the fused kernel are stepped as up to 3 groups of
+ * swarms, each on a stream of the library's own: the groups start after the
+ * work already on the handle's stream and the handle's stream continues after
+ * all of them, so results and ordering are as on one stream (and bit-identical
+ * to stepping the swarms as one group).  One iteration of a group is one launch
+ * per fused-kernel class (instances with the same padded size and symmetry
+ * share a launch), the per-stage kernels of instances outside the int8 path,
+ * and one batched launch each for the swarm bests and the finish step.  The
+ * first call captures each group's iteration into a HIP graph, replayed once
+ * per iteration; a stream that cannot be captured keeps eager launches. */
 int qap_swarm_step(qap_swarm* h, int32_t iterations);
 
-/* *active = 1 if qap_swarm_step replays a captured graph (0: eager launches,
- * before the first step, or while profiling). */
-int qap_swarm_graph(qap_swarm* h, int32_t* active);
+/* *active (may be NULL) = 1 if qap_swarm_step replays captured graphs (0:
+ * eager launches, before the first step, or while profiling); *streams (may be
+ * NULL) = number of stream groups, i.e. concurrent launches of each stage per
+ * iteration. */
+int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams);
 
 /* Wait for the handle's stream. */
 int qap_swarm_sync(qap_swarm* h);
@@ -172,11 +182,12 @@ int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t*
 
 /* Kernel timing for measurement.  enable = 1 switches the handle to
  * profiled stepping: every later qap_swarm_step launches its kernels one by
- * one (no graph) with HIP events recorded on the handle's stream around each
- * stage kernel, and the counters restart from zero; enable = 0 switches back.
+ * one (no graph) with HIP events recorded around each stage on the stream it
+ * runs on, and the counters restart from zero; enable = 0 switches back.
  * stage_ms (QAP_NUM_STAGES doubles, may be NULL) receives the summed kernel
- * time per stage and *launches the number of iterations profiled (waits
- * first).  Stages: QAP_STAGE_SX (S_x), QAP_STAGE_VELOCITY,
+ * time per stage -- summed over the stream groups, whose launches overlap in
+ * time (qap_swarm_graph gives their number) -- and *launches the number of
+ * iterations profiled (waits first).  Stages: QAP_STAGE_SX (S_x), QAP_STAGE_VELOCITY,
  * QAP_STAGE_GOAL_DELTA (goal, deltas, exchange, P^L), QAP_STAGE_FUSED (the
  * whole particle iteration in one kernel), QAP_STAGE_BESTS (swarm bests,
  * best-ever, migration). */

@@ -44,7 +44,7 @@ class qap_params(ctypes.Structure):
                 ("velocity_kernel", ctypes.c_int32), ("st_depth", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("migration_factor", ctypes.c_float), ("migration_period", ctypes.c_int32),
                 ("local_search", ctypes.c_int32), ("delta_path", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p)]
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p), ("stream_groups", ctypes.c_int32)]
 
 
 class qap_state(ctypes.Structure):
@@ -81,7 +81,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_eval.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int64),
                                  P(ctypes.c_int64)]
     L.qap_swarm_path.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
-    L.qap_swarm_graph.argtypes = [vp, P(ctypes.c_int32)]
+    L.qap_swarm_graph.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.qap_swarm_profile.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     L.qap_swarm_destroy.argtypes = [vp]
     L.qap_swarm_destroy.restype = None
@@ -123,7 +123,7 @@ _PATHS = {"auto": QAP_PATH_AUTO, "int8": QAP_PATH_INT8_MFMA, "int32": QAP_PATH_I
 
 def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax=1.0, norm=True, depth=2,
                 migration=False, migration_factor=0.0, migration_period=1, local_search=True, delta_path="auto",
-                engine="fused", seed=1, stream=None) -> qap_params:
+                engine="fused", seed=1, stream=None, stream_groups=0) -> qap_params:
     p = qap_params()
     p.num_swarms = int(num_swarms)
     p.particles_per_swarm = int(particles_per_swarm)
@@ -138,6 +138,7 @@ def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax
     p.engine = _ENGINES[engine] if isinstance(engine, str) else int(engine)
     p.seed = int(seed)
     p.stream = stream
+    p.stream_groups = int(stream_groups)
     return p
 
 
@@ -273,10 +274,16 @@ class Swarm:
         return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32"}[p.value], bool(s.value)
 
     def graph_active(self) -> bool:
-        """Whether stepping replays a captured HIP graph."""
+        """Whether stepping replays captured HIP graphs."""
         a = ctypes.c_int32()
-        _check(load_library().qap_swarm_graph(self.h, ctypes.byref(a)), "qap_swarm_graph")
+        _check(load_library().qap_swarm_graph(self.h, ctypes.byref(a), None), "qap_swarm_graph")
         return bool(a.value)
+
+    def stream_groups(self) -> int:
+        """Concurrent stream groups (launches of each stage per iteration)."""
+        g = ctypes.c_int32()
+        _check(load_library().qap_swarm_graph(self.h, None, ctypes.byref(g)), "qap_swarm_graph")
+        return int(g.value)
 
     def profile(self, enable: bool):
         """Switch profiled stepping on/off; returns ({stage: ms}, iterations) so far."""

@@ -38,6 +38,7 @@ struct InstDesc {
     int zd;         // F and D both have a zero diagonal
     int path;       // 1 int8 MFMA, 2 int32
     uint64_t seed;
+    int swarm_base; // index of this descriptor's first swarm in the instance (random streams, records)
     // instance data
     const int* F32;         // [n][n]
     const int* D32;         // [n][n]

@@ -393,7 +393,8 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
     const int tprev = *d.iter;
     const uint32_t tau = (uint32_t)tprev + 1u;
     const int cur = tprev & 1;
-    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const int gl = k / d.S;  // swarm within this descriptor; g: within the instance
+    const uint32_t g = (uint32_t)(gl + d.swarm_base), s = (uint32_t)(k % d.S);
     const float* Vp = d.V[cur] + (size_t)k * n * n;
     float* Vq = d.V[cur ^ 1] + (size_t)k * n * n;
     const uint8_t* Xk = d.X[cur] + (size_t)k * n;
@@ -422,7 +423,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
             Attract at;
             xr = at.xr = Xk[c];
             at.lr = d.PL[(size_t)k * n + c];
-            at.gr = d.PG[(size_t)g * n + c];
+            at.gr = d.PG[(size_t)gl * n + c];
             at.ax = (float)((at.xr == at.lr) - 1);
             at.bx = (float)((at.xr == at.gr) - 1);
             at.bl = (float)(at.lr == at.gr);

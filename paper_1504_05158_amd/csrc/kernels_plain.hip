@@ -14,7 +14,7 @@ __global__ void k_init_perm(InstDesc d)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= d.P) return;
-    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     const int n = d.n;
     uint8_t* x = d.X[0] + (size_t)k * n;
     for (int j = 0; j < n; ++j) x[j] = (uint8_t)j;
@@ -35,7 +35,7 @@ __global__ void k_init_vel(InstDesc d)
     const int n = d.n;
     if (idx >= (long long)d.P * n) return;
     const int k = (int)(idx / n), c = (int)(idx % n);
-    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     float* V = d.V[0] + (size_t)k * n * n;
     float sum = 0.0f;
     for (int r = 0; r < n; ++r) {
@@ -61,13 +61,14 @@ __global__ void k_velocity(InstDesc d)
     const int tprev = *d.iter;
     const uint32_t tau = (uint32_t)tprev + 1u;
     const int cur = tprev & 1;
-    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const int gl = k / d.S;  // swarm within this descriptor; g: within the instance
+    const uint32_t g = (uint32_t)(gl + d.swarm_base), s = (uint32_t)(k % d.S);
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
     const float s2 = __fmul_rn(d.c2, unit_float(rb.w[0]));
     const float s3 = __fmul_rn(d.c3, unit_float(rb.w[1]));
     const int x = d.X[cur][(size_t)k * n + c];
     const int pl = d.PL[(size_t)k * n + c];
-    const int pg = d.PG[(size_t)g * n + c];
+    const int pg = d.PG[(size_t)gl * n + c];
     const float* Vc = d.V[cur] + (size_t)k * n * n;
     const float sc = d.Vinv[cur][(size_t)k * n + c];
     float* Vn = d.V[cur ^ 1] + (size_t)k * n * n;
@@ -95,7 +96,7 @@ __global__ __launch_bounds__(256) void k_second_target(InstDesc d)
     const int n = d.n;
     const int tprev = *d.iter;
     const int cur = tprev & 1;
-    const uint32_t g = (uint32_t)(k / d.S), s = (uint32_t)(k % d.S);
+    const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     const float* V = d.V[cur] + (size_t)k * n * n;
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     StState<CPL> st;
@@ -393,7 +394,7 @@ __global__ __launch_bounds__(256) void k_finish(const InstDesc* __restrict__ des
         if (tid == 0) {
             d.best->goal = bg;
             d.best->iter = tau;
-            d.best->swarm = bs;
+            d.best->swarm = bs + d.swarm_base;
             d.best->member = mem;
         }
     }

@@ -98,3 +98,22 @@ def test_graph_replays_equal_eager(q, engine):
     assert_same(a.get_state(0), b.get_state(0), "after set_state")
     a.close()
     b.close()
+
+
+def test_stream_groups_bit_identical(q):
+    """Independent swarms stepped as 1, 2 or 3 concurrent stream groups give
+    identical states: the groups only partition the swarms."""
+    F, D = gen.uniform_instance(64, 0, 99, 31)
+    cfg = run_cfg(num_swarms=7, particles_per_swarm=9, seed=17)
+    announce("stream groups")
+    hs = [q.Swarm.create(F, D, engine="fused", stream_groups=g, **cfg) for g in (1, 2, 3)]
+    assert [h.stream_groups() for h in hs] == [1, 2, 3]
+    for it in range(4):
+        for h in hs:
+            h.step(1 + it)
+        ref = hs[0].get_state()
+        for h in hs[1:]:
+            assert_same(h.get_state(), ref, ("groups", h.stream_groups(), "after", it + 1))
+            assert h.best()[0] == hs[0].best()[0]
+    for h in hs:
+        h.close()
