@@ -49,6 +49,7 @@ enum {
 enum { QAP_SV_RAW = 0, QAP_SV_NORM = 1 };          /* S_v of Sec. 3.1 */
 enum { QAP_INDEPENDENT = 0, QAP_MIGRATION = 1 };   /* swarm modes (Sec. 3.2) */
 enum { QAP_PATH_AUTO = 0, QAP_PATH_INT8_MFMA = 1, QAP_PATH_INT32 = 2 }; /* swap-delta contraction */
+enum { QAP_MAX_EXCHANGES = 65535 }; /* largest local_search */
 enum { QAP_ENGINE_FUSED = 0, QAP_ENGINE_PLAIN = 1 }; /* one fused kernel per step vs per-stage kernels */
 
 typedef struct qap_swarm qap_swarm; /* opaque handle */
@@ -67,7 +68,11 @@ typedef struct {
  *  st_depth in [0, n-1]: SecondTarget depth d (Alg. 1, d < n).
  *  mode, migration_factor, migration_period: Alg. 2 with depth
  *    floor(migration_factor * m), which must be < m/2; the period is >= 1.
- *  local_search: 1 = one best-improvement pair exchange per particle-iteration.
+ *  local_search: best-improvement pair exchanges per particle-iteration, 0 to
+ *    QAP_MAX_EXCHANGES: each exchange takes the pair with the smallest delta
+ *    (ties to the smallest a, then b) and is made only if it lowers the goal;
+ *    the first non-improving pair ends the search (a local optimum of the
+ *    pair-exchange neighbourhood; a large value runs to one).
  *  delta_path: contraction used for the pair-exchange deltas (AUTO picks int8
  *    MFMA when every F, D entry is in [-128, 127] and n <= 160; INT8_MFMA with
  *    n > 160 also runs on the int32 path, which qap_swarm_path reports).

@@ -194,7 +194,7 @@ class OracleSwarm:
         self.P = P = self.m * self.S
         self.c1, self.c2, self.c3 = float(np.float32(c1)), float(np.float32(c2)), float(np.float32(c3))
         self.vmax = float(np.float32(vmax))
-        self.norm, self.depth, self.ls = bool(norm), int(depth), bool(local_search)
+        self.norm, self.depth, self.ls = bool(norm), int(depth), int(local_search)  # exchanges per iteration
         self.migration = bool(migration)
         self.migr_d = int(np.floor(np.float32(migration_factor) * self.m)) if migration else 0
         self.period = int(migration_period)

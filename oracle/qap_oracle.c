@@ -405,7 +405,8 @@ void orc_migrate(int n, int m, int S, int d, uint64_t seed, uint32_t t,
  *   1. r2, r3 drawn per particle;
  *   2. X' = SecondTarget(X(t-1) + V(t-1), Z = X(t-1), depth)  (eq. position);
  *   3. V(t) = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X)), all at t-1 (eq. velocity);
- *   4. goal of X'; if local_search, one best-improvement pair exchange;
+ *   4. goal of X'; then up to local_search best-improvement pair exchanges,
+ *      one after another, stopping at the first one that does not improve;
  *   5. P^L <- X(t) on strict improvement (best position so far);
  * then per swarm: P^G <- the current solution of the best member (lowest
  * index on ties) on strict improvement; the best-ever record likewise; and
@@ -439,7 +440,8 @@ void orc_step(int n, const int32_t* F, const int32_t* D, int m, int S,
             memcpy(v, Vn, sizeof(double) * nn);
             int64_t gl = orc_cost(n, F, D, xn);
             if (deltas_out) orc_deltas(n, F, D, xn, deltas_out + (size_t)pi * nn);
-            if (local_search) orc_local_search(n, F, D, xn, &gl, NULL, NULL, NULL);
+            for (int q = 0; q < local_search; ++q)
+                if (!orc_local_search(n, F, D, xn, &gl, NULL, NULL, NULL)) break;
             memcpy(x, xn, sizeof(int32_t) * (size_t)n);
             goal[pi] = gl;
             if (gl < goalPL[pi]) {

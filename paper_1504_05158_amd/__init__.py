@@ -133,7 +133,7 @@ def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax
     p.mode = QAP_MIGRATION if migration else QAP_INDEPENDENT
     p.migration_factor = float(migration_factor)
     p.migration_period = int(migration_period)
-    p.local_search = 1 if local_search else 0
+    p.local_search = int(local_search)  # True -> 1 exchange per particle-iteration
     p.delta_path = _PATHS[delta_path] if isinstance(delta_path, str) else int(delta_path)
     p.engine = _ENGINES[engine] if isinstance(engine, str) else int(engine)
     p.seed = int(seed)

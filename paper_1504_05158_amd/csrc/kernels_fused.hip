@@ -453,10 +453,25 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
     wave_sync();
 
     // ---- C. goal, pair-exchange deltas, one exchange
+    // up to d.ls best-improvement exchanges: each one found while more are
+    // allowed is made in place and the deltas recomputed; the last allowed one
+    // is applied when X(t+1) is written
     long long goal, key;
-    goal_delta_mfma<NP, SYM, ZD>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
+    int swaps = 0;
+    for (;;) {
+        goal_delta_mfma<NP, SYM, ZD>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
+        if (d.ls <= swaps + 1 || key == LLONG_MAX || (key >> 16) >= 0) break;
+        if (l == 0) {
+            const int a = (int)((key >> 8) & 0xff), b = (int)(key & 0xff);
+            const uint8_t t = pw[a];
+            pw[a] = pw[b];
+            pw[b] = t;
+        }
+        wave_sync();
+        ++swaps;
+    }
     int ba = -1, bb = -1;
-    if (d.ls && key != LLONG_MAX) {
+    if (d.ls > swaps && key != LLONG_MAX) {
         const long long del = key >> 16;
         if (del < 0) {
             ba = (int)((key >> 8) & 0xff);

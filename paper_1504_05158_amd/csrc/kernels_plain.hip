@@ -191,6 +191,13 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
         // clamp: a malformed permutation on the device can give wrong numbers, never a stray address
         for (int j = tid; j < n; j += 256) pl[j] = pe[j] < n ? pe[j] : (uint8_t)(n - 1);
         __syncthreads();
+        // step mode: up to d.ls exchanges; one found while more are allowed is
+        // made in pl and everything recomputed, the last allowed one is applied
+        // when X(t+1) is written
+        int swaps = 0;
+        long long goal, bd;
+        int ba, bb;
+        for (;;) {
         gemm_to_scratch<MUL24>(n, d.F32, d.D32, pl, A, Fs, Ds);
         if (GEN) {
             // B[x][y] = sum_k F[k][x] D[p_k][p_y]: the same product on (F^T, D^T)
@@ -241,10 +248,11 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
         gpart = wave_sum_i64(gpart);
         if (l == 0) red_goal[w] = gpart;
         __syncthreads();
-        long long goal = red_goal[0] + red_goal[1] + red_goal[2] + red_goal[3];
+        goal = red_goal[0] + red_goal[1] + red_goal[2] + red_goal[3];
         // pair deltas
-        long long bd = LLONG_MAX;
-        int ba = 0x7fffffff, bb = 0x7fffffff;
+        bd = LLONG_MAX;
+        ba = 0x7fffffff;
+        bb = 0x7fffffff;
         if (mode != 2) {
             for (int q = tid; q < n * n; q += 256) {
                 const int a = q / n, b = q % n;
@@ -279,10 +287,20 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
                     bd = red_d[u]; ba = red_a[u]; bb = red_b[u];
                 }
         }
+        if (mode != 0 || d.ls <= swaps + 1 || ba >= n || bd >= 0) break;
+        __syncthreads();  // every thread has read the reductions
+        if (tid == 0) {
+            const uint8_t t = pl[ba];
+            pl[ba] = pl[bb];
+            pl[bb] = t;
+        }
+        __syncthreads();
+        ++swaps;
+        }
         if (mode == 1) {
             if (tid == 0 && goals_out) goals_out[e] = goal;
         } else {
-            const bool swap = (mode == 0) && d.ls && ba < n && bd < 0;
+            const bool swap = (mode == 0) && d.ls > swaps && ba < n && bd < 0;
             if (swap) goal += bd;
             uint8_t* xo = (mode == 0) ? d.X[cur ^ 1] + (size_t)e * n : nullptr;
             const bool improve = (mode == 2) || goal < d.goalPL[e];

@@ -128,7 +128,7 @@ int check_params(const qap_instance* in, const qap_params* p)
         const long long d = (long long)(p->migration_factor * (float)p->num_swarms);
         if (2 * d >= p->num_swarms && d > 0) return QAP_ERR_INVALID_ARG;
     }
-    if (p->local_search != 0 && p->local_search != 1) return QAP_ERR_INVALID_ARG;
+    if (p->local_search < 0 || p->local_search > QAP_MAX_EXCHANGES) return QAP_ERR_INVALID_ARG;
     if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_INT32) return QAP_ERR_INVALID_ARG;
     if (p->engine != QAP_ENGINE_FUSED && p->engine != QAP_ENGINE_PLAIN) return QAP_ERR_INVALID_ARG;
     if (p->stream_groups < 0 || p->stream_groups > kStreamGroups) return QAP_ERR_INVALID_ARG;

@@ -70,6 +70,9 @@ CASES = [
     dict(n=100, kind="euclid", norm=True, depth=2, ls=True, migration=True),
     dict(n=128, kind="sym", norm=True, depth=2, ls=True),
     dict(n=150, kind="sym", norm=False, depth=5, ls=True),
+    dict(n=40, kind="sym", norm=True, depth=2, ls=3),
+    dict(n=33, kind="gen", norm=True, depth=2, ls=4),
+    dict(n=128, kind="sym", norm=True, depth=2, ls=1000),   # to a pair-exchange local optimum
 ]
 
 
