@@ -185,6 +185,20 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
  * *delta_path, and 1 in *symmetric if F and D are both symmetric. */
 int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric);
 
+/* Population statistics of the current goals of an instance (the percentile
+ * ranks and probability mass functions of Sec. 4.2), computed on the device;
+ * waits.  For each of nq (0..QAP_STATS_MAX_RANKS) ranks q_ppm[j] in parts per
+ * million (1..10^6): the nearest-rank value, i.e. the value at position
+ * ceil(q N / 10^6) (at least 1) of the N goals in ascending order, per swarm
+ * into swarm_q [m][nq] (N = particles per swarm) and over all particles into
+ * pop_q [nq].  For bins (0..QAP_STATS_MAX_BINS) > 0 with lo < hi and
+ * (hi - lo) * bins < 2^62: the number of goals g with lo <= g < hi in bin
+ * floor((g - lo) * bins / (hi - lo)), per swarm into swarm_hist [m][bins] and
+ * over all particles into pop_hist [bins].  Every output may be NULL. */
+enum { QAP_STATS_MAX_RANKS = 64, QAP_STATS_MAX_BINS = 4096 };
+int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                    int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist);
+
 /* Kernel timing for measurement.  enable = 1 switches the handle to
  * profiled stepping: every later qap_swarm_step launches its kernels one by
  * one (no graph) with HIP events recorded around each stage on the stream it

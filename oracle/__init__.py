@@ -177,6 +177,32 @@ def get_threads() -> int:
 
 
 # ---------------------------------------------------------------- swarm state
+def nearest_rank_quantiles(values, q_ppm) -> np.ndarray:
+    """Percentile ranks of a population of goals (Sec. 4.2): for q in parts per
+    million, the value at position ceil(q * N / 10^6) (at least 1) of the values
+    in ascending order -- the nearest-rank reading of the paper's percentile
+    ranks.  Integer arithmetic throughout."""
+    v = np.sort(np.asarray(values, np.int64))
+    N = len(v)
+    out = []
+    for q in q_ppm:
+        r = max(1, -(-int(q) * N // 1000000))  # ceil(q N / 10^6)
+        out.append(v[min(r, N) - 1])
+    return np.asarray(out, np.int64)
+
+
+def goal_histogram(values, bins: int, lo: int, hi: int) -> np.ndarray:
+    """Probability mass function of goals as counts (Sec. 4.2): bin
+    floor((g - lo) * bins / (hi - lo)) for lo <= g < hi; values outside
+    [lo, hi) are not counted."""
+    h = np.zeros(bins, np.int64)
+    for g in np.asarray(values, np.int64):
+        g = int(g)
+        if lo <= g < hi:
+            h[(g - lo) * bins // (hi - lo)] += 1
+    return h
+
+
 class OracleSwarm:
     """Whole-run oracle: state arrays in the layout the GPU library exports.
 

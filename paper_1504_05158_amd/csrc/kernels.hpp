@@ -43,4 +43,14 @@ bool fused_supported(const InstDesc& d);
 hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
                             long long* deltas, hipStream_t st);
 
+// Population statistics.  launch_select: for every segment s (values
+// [seg_off[s], seg_off[s+1])) and rank j, out[s*nr + j] = the value at
+// 1-based position ranks[s*nr + j] in ascending order.  launch_hist:
+// out[s*bins + i] = number of values g of segment s with lo <= g < hi and
+// ((g - lo) * bins) / (hi - lo) == i.  All pointers are device memory.
+hipError_t launch_select(const long long* values, const int* seg_off, int nseg, const long long* ranks, int nr,
+                         long long* out, hipStream_t st);
+hipError_t launch_hist(const long long* values, const int* seg_off, int nseg, int bins, long long lo, long long hi,
+                       unsigned long long* out, hipStream_t st);
+
 }  // namespace qap

@@ -1,0 +1,90 @@
+// Population statistics of goals (Sec. 4.2): percentile ranks and PMF counts,
+// per swarm and over the whole population, computed on demand.
+//
+// k_select: the value of a given rank in a segment of int64 values, by an
+// MSD radix select over the 64-bit key (sign bit flipped, which orders signed
+// values as unsigned): 8 passes, each counting the next byte of the keys that
+// share the prefix fixed so far (LDS histogram), then descending into the byte
+// that holds the rank.  One workgroup per (segment, rank).
+//
+// k_hist: per segment, the counts of values in bins ((g - lo) * bins) / (hi - lo)
+// for lo <= g < hi, accumulated in LDS.  One workgroup per segment.
+#include "kernels.hpp"
+
+namespace qap {
+
+__global__ __launch_bounds__(256) void k_select(const long long* __restrict__ values, const int* __restrict__ seg_off,
+                                                const long long* __restrict__ ranks, int nr,
+                                                long long* __restrict__ out)
+{
+    __shared__ unsigned cnt[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ long long s_rank;
+    const int seg = (int)blockIdx.x / nr;
+    const int b = seg_off[seg], e = seg_off[seg + 1];
+    long long r = ranks[blockIdx.x];  // 1-based, 1 <= r <= e - b (checked on the host)
+    unsigned long long prefix = 0, mask = 0;
+    for (int pass = 0; pass < 8; ++pass) {
+        const int shift = 56 - 8 * pass;
+        for (int i = threadIdx.x; i < 256; i += blockDim.x) cnt[i] = 0;
+        __syncthreads();
+        for (int i = b + (int)threadIdx.x; i < e; i += blockDim.x) {
+            const unsigned long long key = (unsigned long long)values[i] ^ (1ull << 63);
+            if ((key & mask) == prefix) atomicAdd(&cnt[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            long long rr = r;
+            int digit = 0;
+            while (digit < 255 && rr > (long long)cnt[digit]) {
+                rr -= cnt[digit];
+                ++digit;
+            }
+            s_prefix = prefix | ((unsigned long long)digit << shift);
+            s_rank = rr;
+        }
+        __syncthreads();
+        prefix = s_prefix;
+        r = s_rank;
+        mask |= 255ull << shift;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = (long long)(prefix ^ (1ull << 63));
+}
+
+__global__ __launch_bounds__(256) void k_hist(const long long* __restrict__ values, const int* __restrict__ seg_off,
+                                              int bins, long long lo, long long hi,
+                                              unsigned long long* __restrict__ out)
+{
+    extern __shared__ unsigned hist[];
+    const int seg = (int)blockIdx.x;
+    const int b = seg_off[seg], e = seg_off[seg + 1];
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const long long width = hi - lo;
+    for (int i = b + (int)threadIdx.x; i < e; i += blockDim.x) {
+        const long long g = values[i];
+        if (g >= lo && g < hi) atomicAdd(&hist[(int)(((g - lo) * bins) / width)], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < bins; i += blockDim.x) out[(size_t)seg * bins + i] = hist[i];
+}
+
+hipError_t launch_select(const long long* values, const int* seg_off, int nseg, const long long* ranks, int nr,
+                         long long* out, hipStream_t st)
+{
+    if (nseg <= 0 || nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_select, dim3((unsigned)(nseg * nr)), dim3(256), 0, st, values, seg_off, ranks, nr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hist(const long long* values, const int* seg_off, int nseg, int bins, long long lo, long long hi,
+                       unsigned long long* out, hipStream_t st)
+{
+    if (nseg <= 0 || bins <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist, dim3((unsigned)nseg), dim3(256), sizeof(unsigned) * (size_t)bins, st, values, seg_off,
+                       bins, lo, hi, out);
+    return hipGetLastError();
+}
+
+}  // namespace qap

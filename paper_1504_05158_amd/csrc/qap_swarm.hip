@@ -891,6 +891,75 @@ int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* l
     return QAP_OK;
 }
 
+int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                    int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (nq < 0 || nq > QAP_STATS_MAX_RANKS || (nq > 0 && !q_ppm)) return QAP_ERR_INVALID_ARG;
+    for (int j = 0; j < nq; ++j)
+        if (q_ppm[j] < 1 || q_ppm[j] > 1000000) return QAP_ERR_INVALID_ARG;
+    if (bins < 0 || bins > QAP_STATS_MAX_BINS) return QAP_ERR_INVALID_ARG;
+    if (bins > 0 && (!(lo < hi) || (unsigned long long)hi - (unsigned long long)lo > (1ull << 62) / (unsigned)bins))
+        return QAP_ERR_INVALID_ARG;
+    const int m = I->m, S = I->S, P = I->P;
+    const bool want_q = nq > 0 && (swarm_q || pop_q), want_h = bins > 0 && (swarm_hist || pop_hist);
+    if (!want_q && !want_h) return QAP_OK;
+    // segments: the m swarms, then the whole population
+    std::vector<int> off((size_t)m + 3);
+    for (int g = 0; g <= m; ++g) off[(size_t)g] = g * S;
+    off[(size_t)m + 1] = 0;
+    off[(size_t)m + 2] = P;
+    const int nr = std::max(nq, 1);
+    std::vector<long long> ranks((size_t)(m + 1) * nr, 1);
+    for (int j = 0; j < nq; ++j) {
+        const auto rank = [&](long long N) { return std::max(1LL, ((long long)q_ppm[j] * N + 999999) / 1000000); };
+        for (int g = 0; g < m; ++g) ranks[(size_t)g * nr + j] = rank(S);
+        ranks[(size_t)m * nr + j] = rank(P);
+    }
+    const size_t b_off = off.size() * sizeof(int), b_rank = ranks.size() * sizeof(long long);
+    const size_t b_out = ranks.size() * sizeof(long long), b_hist = (size_t)m * std::max(bins, 1) * 8;
+    char* buf = nullptr;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMalloc(&buf, b_off + b_rank + b_out + b_hist);
+    if (e != hipSuccess) return dev_err(h, e);
+    int* d_off = (int*)buf;
+    long long* d_rank = (long long*)(buf + b_off);
+    long long* d_out = (long long*)(buf + b_off + b_rank);
+    unsigned long long* d_hist = (unsigned long long*)(buf + b_off + b_rank + b_out);
+    std::vector<long long> outq(ranks.size());
+    std::vector<unsigned long long> hist((size_t)m * std::max(bins, 1));
+    e = hipMemcpy(d_off, off.data(), b_off, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_rank, ranks.data(), b_rank, hipMemcpyHostToDevice);
+    if (e == hipSuccess && want_q) e = qap::launch_select(I->d.goal, d_off, m, d_rank, nr, d_out, h->stream);
+    if (e == hipSuccess && want_q)
+        e = qap::launch_select(I->d.goal, d_off + m + 1, 1, d_rank + (size_t)m * nr, nr, d_out + (size_t)m * nr,
+                               h->stream);
+    if (e == hipSuccess && want_h) e = qap::launch_hist(I->d.goal, d_off, m, bins, lo, hi, d_hist, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess && want_q) e = hipMemcpy(outq.data(), d_out, b_out, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && want_h) e = hipMemcpy(hist.data(), d_hist, b_hist, hipMemcpyDeviceToHost);
+    (void)hipFree(buf);
+    if (e != hipSuccess) return dev_err(h, e);
+    for (int j = 0; j < nq; ++j) {
+        if (swarm_q)
+            for (int g = 0; g < m; ++g) swarm_q[(size_t)g * nq + j] = outq[(size_t)g * nr + j];
+        if (pop_q) pop_q[j] = outq[(size_t)m * nr + j];
+    }
+    if (want_h) {
+        if (pop_hist)
+            for (int i = 0; i < bins; ++i) pop_hist[i] = 0;
+        for (int g = 0; g < m; ++g)
+            for (int i = 0; i < bins; ++i) {
+                const long long c = (long long)hist[(size_t)g * bins + i];
+                if (swarm_hist) swarm_hist[(size_t)g * bins + i] = c;
+                if (pop_hist) pop_hist[i] += c;
+            }
+    }
+    return QAP_OK;
+}
+
 int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
