@@ -50,6 +50,7 @@ enum { QAP_SV_RAW = 0, QAP_SV_NORM = 1 };          /* S_v of Sec. 3.1 */
 enum { QAP_INDEPENDENT = 0, QAP_MIGRATION = 1 };   /* swarm modes (Sec. 3.2) */
 enum { QAP_PATH_AUTO = 0, QAP_PATH_INT8_MFMA = 1, QAP_PATH_INT32 = 2 }; /* swap-delta contraction */
 enum { QAP_MAX_EXCHANGES = 65535 }; /* largest local_search */
+enum { QAP_SX_SECOND_TARGET = 0, QAP_SX_PICK_COLUMN = 1 }; /* S_x procedures */
 enum { QAP_ENGINE_FUSED = 0, QAP_ENGINE_PLAIN = 1 }; /* one fused kernel per step vs per-stage kernels */
 
 typedef struct qap_swarm qap_swarm; /* opaque handle */
@@ -81,6 +82,10 @@ typedef struct {
  *    kernel per stage, int32 contraction).
  *  seed: key of the random stream.  stream: hipStream_t to run on (NULL = the
  *    library's own stream).
+ *  sx_procedure: QAP_SX_SECOND_TARGET (Alg. 1 with st_depth; st_depth = 0 is the
+ *    paper's GlobalMax) or QAP_SX_PICK_COLUMN (columns visited in a random
+ *    order, each taking its largest key over the rows left; runs on the
+ *    per-stage kernels, whatever the engine).
  *  stream_groups: 0 = automatic (independent swarms on the fused kernel are
  *    stepped as up to 3 concurrent groups of swarms, see qap_swarm_step), or 1-3
  *    to set the number of groups (results are the same for every choice). */
@@ -100,6 +105,7 @@ typedef struct {
     uint64_t seed;
     void* stream;
     int32_t stream_groups;
+    int32_t sx_procedure;
 } qap_params;
 
 /* Host-side copy of one instance's state (checkpoint / inspection).  Every

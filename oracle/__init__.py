@@ -73,8 +73,9 @@ def lib():
                                _i32p, _i32p]
         L.orc_migrate.argtypes = [_c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_uint64, _c.c_uint32,
                                   _i32p, _i64p, _i32p, _i64p]
+        L.orc_pick_column.argtypes = [_c.c_int, _f32p, _c.c_uint64, _c.c_uint32, _c.c_uint32, _c.c_uint32, _i32p]
         L.orc_step.argtypes = [_c.c_int, _i32p, _i32p, _c.c_int, _c.c_int, _c.c_double, _c.c_double,
-                               _c.c_double, _c.c_double, _c.c_int, _c.c_int, _c.c_int, _c.c_int,
+                               _c.c_double, _c.c_double, _c.c_int, _c.c_int, _c.c_int, _c.c_int, _c.c_int,
                                _c.c_int, _c.c_int, _c.c_uint64, _c.c_int32, _f64p, _i32p, _i32p,
                                _i64p, _i64p, _i32p, _i64p, _i64p, _i32p, _i32p, _c.c_void_p]
         L.orc_set_threads.argtypes = [_c.c_int]
@@ -168,6 +169,14 @@ def second_target(W, z, depth, seed=0, t=1, particle=0, swarm=0, return_ties=Fal
     return (out, ties) if return_ties else out
 
 
+def pick_column(W, seed=0, t=1, particle=0, swarm=0):
+    W = np.ascontiguousarray(W, dtype=np.float32)
+    n = W.shape[0]
+    out = np.full(n, -1, np.int32)
+    lib().orc_pick_column(n, W, seed, t, particle, swarm, out)
+    return out
+
+
 def set_threads(k: int) -> None:
     lib().orc_set_threads(int(k))
 
@@ -213,7 +222,7 @@ class OracleSwarm:
 
     def __init__(self, F, D, *, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax=1.0,
                  norm=True, depth=2, local_search=True, migration=False, migration_factor=0.0,
-                 migration_period=1, seed=1):
+                 migration_period=1, seed=1, sx="second_target"):
         self.F, self.D = _i32(F), _i32(D)
         self.n = n = self.F.shape[0]
         self.m, self.S = int(num_swarms), int(particles_per_swarm)
@@ -221,6 +230,7 @@ class OracleSwarm:
         self.c1, self.c2, self.c3 = float(np.float32(c1)), float(np.float32(c2)), float(np.float32(c3))
         self.vmax = float(np.float32(vmax))
         self.norm, self.depth, self.ls = bool(norm), int(depth), int(local_search)  # exchanges per iteration
+        self.sx = {"second_target": 0, "pick_column": 1}[sx]
         self.migration = bool(migration)
         self.migr_d = int(np.floor(np.float32(migration_factor) * self.m)) if migration else 0
         self.period = int(migration_period)
@@ -249,7 +259,7 @@ class OracleSwarm:
                 assert deltas_out.shape == (self.P, self.n, self.n)
                 dptr = deltas_out.ctypes.data_as(ctypes.c_void_p)
             lib().orc_step(self.n, self.F, self.D, self.m, self.S, self.c1, self.c2, self.c3, self.vmax,
-                           int(self.norm), self.depth, int(self.ls), int(self.migration), self.migr_d,
+                           int(self.norm), self.depth, self.sx, int(self.ls), int(self.migration), self.migr_d,
                            self.period, self.seed, self.t, self.V, self.X, self.PL, self.goal,
                            self.goalPL, self.PG, self.goalPG, self.best_goal, self.best_perm,
                            self.best_info, dptr)

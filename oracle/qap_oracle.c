@@ -192,6 +192,55 @@ int orc_local_search(int n, const int32_t* F, const int32_t* D, int32_t* p, int6
     return 0;
 }
 
+/* S_x = PickColumn (the second of the three S_x procedures of Sec. 3.1): the
+ * columns are visited in a random order and each visited column takes its
+ * largest key over the rows not yet taken.  Reading: the order is a
+ * Fisher-Yates shuffle of 0 .. n-1 drawn from the particle's stream (for
+ * i = n-1 .. 1, swap positions i and bounded(element 4 + n + (n-1-i), i+1)),
+ * and equal largest keys in a column go to the k-th such row (ascending),
+ * k = bounded(element 4 + v, count) for the v-th visit, as in SecondTarget.
+ * There is no depth: cells of X(t) take part like any other.               */
+void orc_pick_column(int n, const float* W, uint64_t seed, uint32_t t, uint32_t particle, uint32_t swarm,
+                     int32_t* out)
+{
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    unsigned char* rowAlive = (unsigned char*)malloc((size_t)n);
+    memset(rowAlive, 1, (size_t)n);
+    for (int c = 0; c < n; ++c) order[c] = c;
+    for (int i = n - 1; i >= 1; --i) {
+        const uint32_t j = orc_bounded(orc_word(seed, 4u + (uint32_t)n + (uint32_t)(n - 1 - i), t, particle, swarm),
+                                       (uint32_t)(i + 1));
+        const int32_t tmp = order[i];
+        order[i] = order[j];
+        order[j] = tmp;
+    }
+    for (int v = 0; v < n; ++v) {
+        const int c = order[v];
+        float best = -INFINITY;
+        int found = 0;
+        uint32_t count = 0;
+        for (int r = 0; r < n; ++r) {
+            if (!rowAlive[r]) continue;
+            const float key = W[r * n + c];
+            if (!found || key > best) { best = key; found = 1; count = 0; }
+            if (key == best) ++count;
+        }
+        uint32_t k = 0;
+        if (count > 1) k = orc_bounded(orc_word(seed, 4u + (uint32_t)v, t, particle, swarm), count);
+        int sel = -1;
+        uint32_t seen = 0;
+        for (int r = 0; r < n && sel < 0; ++r) {
+            if (!rowAlive[r] || W[r * n + c] != best) continue;
+            if (seen == k) sel = r;
+            ++seen;
+        }
+        out[c] = sel;
+        rowAlive[sel] = 0;
+    }
+    free(order);
+    free(rowAlive);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Velocity update, eq. (velocity), with the aggregation S_v of Sec. 3.1:
  *   V' = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X)).
@@ -403,7 +452,8 @@ void orc_migrate(int n, int m, int S, int d, uint64_t seed, uint32_t t,
 /* One iteration t-1 -> t of every particle (the step that produces
  * iteration t >= 1), in the order of Sec. 3.1:
  *   1. r2, r3 drawn per particle;
- *   2. X' = SecondTarget(X(t-1) + V(t-1), Z = X(t-1), depth)  (eq. position);
+ *   2. X' = SecondTarget(X(t-1) + V(t-1), Z = X(t-1), depth)  (eq. position),
+ *      or PickColumn(X(t-1) + V(t-1)) when sx = 1;
  *   3. V(t) = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X)), all at t-1 (eq. velocity);
  *   4. goal of X'; then up to local_search best-improvement pair exchanges,
  *      one after another, stopping at the first one that does not improve;
@@ -414,7 +464,7 @@ void orc_migrate(int n, int m, int S, int d, uint64_t seed, uint32_t t,
  * deltas_out (optional, [P][n][n]) receives the pair-exchange deltas of X'
  * before the exchange.                                                      */
 void orc_step(int n, const int32_t* F, const int32_t* D, int m, int S,
-              double c1, double c2, double c3, double vmax, int norm, int depth, int local_search,
+              double c1, double c2, double c3, double vmax, int norm, int depth, int sx, int local_search,
               int migrate, int migr_d, int period, uint64_t seed, int32_t t,
               double* V, int32_t* X, int32_t* PL, int64_t* goal, int64_t* goalPL,
               int32_t* PG, int64_t* goalPG, int64_t* best_goal, int32_t* best_perm, int32_t* best_info,
@@ -435,7 +485,10 @@ void orc_step(int n, const int32_t* F, const int32_t* D, int m, int S,
             int32_t* x = X + pi * n;
             double* v = V + (size_t)pi * nn;
             orc_keys(n, v, x, W);
-            orc_second_target(n, W, x, depth, seed, (uint32_t)t, s, g, xn, NULL);
+            if (sx == 1)
+                orc_pick_column(n, W, seed, (uint32_t)t, s, g, xn);
+            else
+                orc_second_target(n, W, x, depth, seed, (uint32_t)t, s, g, xn, NULL);
             orc_velocity(n, v, x, PL + pi * n, PG + (size_t)g * n, c1, c2, c3, r2, r3, vmax, norm, Vn);
             memcpy(v, Vn, sizeof(double) * nn);
             int64_t gl = orc_cost(n, F, D, xn);

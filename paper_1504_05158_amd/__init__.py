@@ -45,7 +45,8 @@ class qap_params(ctypes.Structure):
                 ("velocity_kernel", ctypes.c_int32), ("st_depth", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("migration_factor", ctypes.c_float), ("migration_period", ctypes.c_int32),
                 ("local_search", ctypes.c_int32), ("delta_path", ctypes.c_int32), ("engine", ctypes.c_int32),
-                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p), ("stream_groups", ctypes.c_int32)]
+                ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p), ("stream_groups", ctypes.c_int32),
+                ("sx_procedure", ctypes.c_int32)]
 
 
 class qap_state(ctypes.Structure):
@@ -127,7 +128,7 @@ _PATHS = {"auto": QAP_PATH_AUTO, "int8": QAP_PATH_INT8_MFMA, "int32": QAP_PATH_I
 
 def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax=1.0, norm=True, depth=2,
                 migration=False, migration_factor=0.0, migration_period=1, local_search=True, delta_path="auto",
-                engine="fused", seed=1, stream=None, stream_groups=0) -> qap_params:
+                engine="fused", seed=1, stream=None, stream_groups=0, sx="second_target") -> qap_params:
     p = qap_params()
     p.num_swarms = int(num_swarms)
     p.particles_per_swarm = int(particles_per_swarm)
@@ -143,6 +144,7 @@ def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax
     p.seed = int(seed)
     p.stream = stream
     p.stream_groups = int(stream_groups)
+    p.sx_procedure = {"second_target": 0, "pick_column": 1}[sx] if isinstance(sx, str) else int(sx)
     return p
 
 

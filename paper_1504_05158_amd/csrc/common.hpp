@@ -32,6 +32,7 @@ struct InstDesc {
     float c1, c2, c3, vmax;
     int norm;       // S_v: 0 raw, 1 column-normalised
     int depth;      // SecondTarget depth
+    int sx;         // S_x procedure: 0 SecondTarget, 1 PickColumn
     int ls;         // one pair exchange per iteration
     int migrate, migr_d, period;
     int sym;        // F and D both symmetric

@@ -553,7 +553,7 @@ static hipError_t fused_launch_np(int npad, const InstDesc* one, const InstDesc*
     }
 }
 
-bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160; }
+bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160 && d.sx == 0; }
 
 hipError_t launch_fused_class(int npad, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st)

@@ -105,9 +105,100 @@ __global__ __launch_bounds__(256) void k_second_target(InstDesc d)
                    (uint32_t)tprev + 1u, s, g);
 }
 
+// S_x = PickColumn, one wave per particle: the visit order (Fisher-Yates on
+// stream elements 4 + n + j, drawn in parallel by the lanes and applied by
+// lane 0 in LDS), then per visited column the largest key over the rows left
+// (a wave maximum over lane-owned rows), equal keys to the k-th such row with
+// k = bounded(stream element 4 + visit, count).
+template <int CPL>
+__global__ __launch_bounds__(256) void k_pick_column(InstDesc d)
+{
+    __shared__ uint32_t swords[4][kMaxN];
+    __shared__ uint8_t sorder[4][kMaxN];
+    const int wl = (int)(threadIdx.x / kWave);
+    const int wave = (int)(blockIdx.x * (blockDim.x / kWave)) + wl;
+    if (wave >= d.P) return;
+    const int k = wave, l = lane_id();
+    const int n = d.n;
+    const int tprev = *d.iter;
+    const int cur = tprev & 1;
+    const uint32_t tau = (uint32_t)tprev + 1u;
+    const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
+    const float* V = d.V[cur] + (size_t)k * n * n;
+    const float* Vs = d.Vinv[cur] + (size_t)k * n;
+    const uint8_t* z = d.X[cur] + (size_t)k * n;
+    uint8_t* out = d.Xnew + (size_t)k * n;
+    uint32_t* w = swords[wl];
+    uint8_t* order = sorder[wl];
+    for (int j = l; j < n - 1; j += kWave) w[j] = stream_word(d.seed, 4u + (uint32_t)(n + j), tau, s, g);
+    for (int c = l; c < n; c += kWave) order[c] = (uint8_t)c;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (l == 0)
+        for (int i = n - 1; i >= 1; --i) {
+            const uint32_t jj = bounded_u32(w[n - 1 - i], (uint32_t)(i + 1));
+            const uint8_t t = order[i];
+            order[i] = order[jj];
+            order[jj] = t;
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned rowbits = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j)
+        if (l + kWave * j < n) rowbits |= 1u << j;
+    for (int v = 0; v < n; ++v) {
+        const int c = order[v];
+        const int zc = z[c];
+        const float sc = Vs[c];
+        float key[CPL];
+        float best = -INFINITY;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            const int r = l + kWave * j;
+            key[j] = -INFINITY;
+            if ((rowbits >> j) & 1u) {
+                const float x = __fmul_rn(V[(size_t)r * n + c], sc);
+                key[j] = r == zc ? 1.0f + x : x;
+            }
+            best = fmaxf(best, key[j]);
+        }
+        const float m = wave_max(best);
+        uint64_t bal[CPL];
+        int count = 0;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            bal[j] = ballot64(((rowbits >> j) & 1u) && key[j] == m);
+            count += __popcll(bal[j]);
+        }
+        int kk = count > 1 ? (int)bounded_u32(stream_word(d.seed, 4u + (uint32_t)v, tau, s, g), (uint32_t)count) : 0;
+        int sel = -1;
+#pragma unroll
+        for (int j = 0; j < CPL; ++j) {
+            if (sel >= 0) continue;
+            const int pc = __popcll(bal[j]);
+            if (kk < pc) {
+                uint64_t b = bal[j];
+                for (int q = 0; q < kk; ++q) b &= b - 1;  // drop the kk lowest set bits
+                sel = kWave * j + __ffsll((long long)b) - 1;
+            } else {
+                kk -= pc;
+            }
+        }
+        if (sel < 0 || sel >= n) sel = 0;  // unreachable: the column has an alive row
+        if (l == 0) out[c] = (uint8_t)sel;
+        if (l == (sel & (kWave - 1))) rowbits &= ~(1u << (sel >> 6));
+    }
+}
+
 template __global__ void k_second_target<1>(InstDesc);
 template __global__ void k_second_target<2>(InstDesc);
 template __global__ void k_second_target<4>(InstDesc);
+template __global__ void k_pick_column<1>(InstDesc);
+template __global__ void k_pick_column<2>(InstDesc);
+template __global__ void k_pick_column<4>(InstDesc);
 
 // ------------------------------------------------------------------ goal + deltas (int32)
 // One workgroup (256 threads) per particle.  A = F . Dp^T with Dp[y][k] =
@@ -489,10 +580,18 @@ hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, hipStrea
     hipError_t e;
 #define REC(i) do { if (ev) { e = hipEventRecord(ev[i], st); if (e != hipSuccess) return e; } } while (0)
     REC(0);
-    switch (cpl) {
-    case 1: hipLaunchKernelGGL(k_second_target<1>, gst, bst, 0, st, d); break;
-    case 2: hipLaunchKernelGGL(k_second_target<2>, gst, bst, 0, st, d); break;
-    default: hipLaunchKernelGGL(k_second_target<4>, gst, bst, 0, st, d); break;
+    if (d.sx == 1) {
+        switch (cpl) {
+        case 1: hipLaunchKernelGGL(k_pick_column<1>, gst, bst, 0, st, d); break;
+        case 2: hipLaunchKernelGGL(k_pick_column<2>, gst, bst, 0, st, d); break;
+        default: hipLaunchKernelGGL(k_pick_column<4>, gst, bst, 0, st, d); break;
+        }
+    } else {
+        switch (cpl) {
+        case 1: hipLaunchKernelGGL(k_second_target<1>, gst, bst, 0, st, d); break;
+        case 2: hipLaunchKernelGGL(k_second_target<2>, gst, bst, 0, st, d); break;
+        default: hipLaunchKernelGGL(k_second_target<4>, gst, bst, 0, st, d); break;
+        }
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;

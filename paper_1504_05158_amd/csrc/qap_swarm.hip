@@ -132,6 +132,7 @@ int check_params(const qap_instance* in, const qap_params* p)
     if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_INT32) return QAP_ERR_INVALID_ARG;
     if (p->engine != QAP_ENGINE_FUSED && p->engine != QAP_ENGINE_PLAIN) return QAP_ERR_INVALID_ARG;
     if (p->stream_groups < 0 || p->stream_groups > kStreamGroups) return QAP_ERR_INVALID_ARG;
+    if (p->sx_procedure != QAP_SX_SECOND_TARGET && p->sx_procedure != QAP_SX_PICK_COLUMN) return QAP_ERR_INVALID_ARG;
     return QAP_OK;
 }
 
@@ -162,7 +163,8 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
     } else {
         pth = f8 ? 1 : 2;
     }
-    if (engine == QAP_ENGINE_PLAIN || n > 160) pth = 2;  // the fused kernel covers n <= 160
+    if (engine == QAP_ENGINE_PLAIN || n > 160 || p->sx_procedure == QAP_SX_PICK_COLUMN)
+        pth = 2;  // the fused kernel covers SecondTarget with n <= 160
     *path = pth;
     *sym = s ? 1 : 0;
     *mul24 = (mf < (1LL << 23) && md < (1LL << 23)) ? 1 : 0;
@@ -188,6 +190,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     d.c1 = p->c1; d.c2 = p->c2; d.c3 = p->c3; d.vmax = p->vmax;
     d.norm = p->velocity_kernel == QAP_SV_NORM;
     d.depth = p->st_depth;
+    d.sx = p->sx_procedure;
     d.ls = p->local_search;
     d.migrate = p->mode == QAP_MIGRATION;
     d.migr_d = d.migrate ? (int)(p->migration_factor * (float)I.m) : 0;

@@ -266,3 +266,43 @@ def test_norm_run_with_column_scales_n128(q, orc, engine):
         sw.step(1)
         assert_states_equal(sw.get_state(), o.state(), what="iteration %d" % (it + 1))
     sw.close()
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("n", [12, 40, 128, 150])
+def test_pick_column_one_step_parity(q, orc, engine, n):
+    """S_x = PickColumn (runs on the per-stage kernels for both engines):
+    re-synchronised one-step parity, integers exact and V within tolerance."""
+    F, D = gen.uniform_instance(n, 0, 127, 600 + n)
+    cfg = run_cfg(num_swarms=2, particles_per_swarm=6, seed=n + 1, sx="pick_column")
+    announce("pickcolumn", engine, n)
+    sw = make_gpu(q, F, D, dict(cfg, engine=engine))
+    assert sw.path()[0] == "int32"
+    for it in range(3):
+        st = sw.get_state()
+        o = oracle_from_state(orc, F, D, cfg, st)
+        o.step()
+        sw.step(1)
+        assert_states_equal(sw.get_state(), o.state(), what="pickcolumn n=%d iteration %d" % (n, it + 1))
+    sw.close()
+
+
+def test_pick_column_with_exact_ties(q, orc):
+    """Quantised velocities: many equal keys inside the visited columns."""
+    n = 40
+    F, D = gen.uniform_instance(n, 0, 20, 9)
+    cfg = run_cfg(num_swarms=2, particles_per_swarm=8, norm=False, local_search=False, seed=5, sx="pick_column")
+    announce("pickcolumn ties")
+    sw = make_gpu(q, F, D, dict(cfg, engine="fused"))
+    st = sw.get_state()
+    rng = np.random.default_rng(3)
+    V = (rng.integers(-2, 3, size=(16, n, n)) / 2.0).astype(np.float32)
+    st["V"] = V
+    sw.set_state(st)
+    sw.step(1)
+    g = sw.get_state()
+    for k in range(16):
+        ref = orc.pick_column(orc.keys(V[k].astype(np.float64), st["X"][k]), seed=5, t=st["t"] + 1, particle=k % 8,
+                              swarm=k // 8)
+        assert np.array_equal(g["X"][k], ref), k
+    sw.close()
