@@ -194,7 +194,7 @@ def cpu_baseline(target_s: float = 15.0, max_steps: int = 50):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--engine", default="fused", choices=["fused", "plain"])
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
