@@ -48,7 +48,7 @@ enum {
 
 enum { QAP_SV_RAW = 0, QAP_SV_NORM = 1 };          /* S_v of Sec. 3.1 */
 enum { QAP_INDEPENDENT = 0, QAP_MIGRATION = 1 };   /* swarm modes (Sec. 3.2) */
-enum { QAP_PATH_AUTO = 0, QAP_PATH_INT8_MFMA = 1, QAP_PATH_INT32 = 2 }; /* swap-delta contraction */
+enum { QAP_PATH_AUTO = 0, QAP_PATH_INT8_MFMA = 1, QAP_PATH_INT32 = 2, QAP_PATH_SPLIT_MFMA = 3 }; /* swap-delta contraction */
 enum { QAP_MAX_EXCHANGES = 65535 }; /* largest local_search */
 enum { QAP_SX_SECOND_TARGET = 0, QAP_SX_PICK_COLUMN = 1 }; /* S_x procedures */
 enum { QAP_ENGINE_FUSED = 0, QAP_ENGINE_PLAIN = 1 }; /* one fused kernel per step vs per-stage kernels */
@@ -74,11 +74,19 @@ typedef struct {
  *    (ties to the smallest a, then b) and is made only if it lowers the goal;
  *    the first non-improving pair ends the search (a local optimum of the
  *    pair-exchange neighbourhood; a large value runs to one).
- *  delta_path: contraction used for the pair-exchange deltas (AUTO picks int8
- *    MFMA when every F, D entry is in [-128, 127] and n <= 160; INT8_MFMA with
- *    n > 160 also runs on the int32 path, which qap_swarm_path reports).
- *  engine: QAP_ENGINE_FUSED (one kernel per step for int8 instances, per-stage
- *    kernels otherwise; steps replay a HIP graph) or QAP_ENGINE_PLAIN (one
+ *  delta_path: contraction used for the pair-exchange deltas, all exact.
+ *    INT8_MFMA: every F, D entry in [-128, 127].  SPLIT_MFMA: F and D
+ *    symmetric, every entry in [-16384, 16383] and
+ *    8 (n + 3) max|F| max|D| < 2^31; each matrix outside the int8 range is
+ *    split into a low plane (M mod 128) and a high plane (floor(M / 128)) and
+ *    the plane products are int8 MFMAs combined in int32.  INT32: any instance
+ *    with n max|F| max|D| < 2^31, on VALU.  A requested MFMA path that the
+ *    instance does not meet fails with QAP_ERR_RANGE.  AUTO picks int8, else
+ *    byte-split, else int32.  The MFMA paths need the fused engine, n <= 160
+ *    and SecondTarget; otherwise the instance runs on the int32 path, which
+ *    qap_swarm_path reports.
+ *  engine: QAP_ENGINE_FUSED (one kernel per step for int8 and byte-split
+ *    instances, per-stage kernels otherwise; steps replay a HIP graph) or QAP_ENGINE_PLAIN (one
  *    kernel per stage, int32 contraction).
  *  seed: key of the random stream.  stream: hipStream_t to run on (NULL = the
  *    library's own stream).
@@ -133,7 +141,8 @@ typedef struct {
 /* Create a handle for one instance and run the initialisation (iteration 0:
  * random permutations, random velocities passed through S_v, goals, bests).
  * Errors: QAP_ERR_INVALID_ARG (NULL, n outside [2,256], a parameter outside
- * the ranges above), QAP_ERR_RANGE (int8 path requested on wider data, or
+ * the ranges above), QAP_ERR_RANGE (an MFMA path requested that the data do
+ * not meet, or
  * n * max|F| * max|D| >= 2^31 so no exact int32 contraction exists),
  * QAP_ERR_NOMEM, QAP_ERR_DEVICE.  On error *out is NULL. */
 int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out);
@@ -187,8 +196,9 @@ int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st);
 int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count,
                    int64_t* goals, int64_t* deltas);
 
-/* Path actually used by an instance: QAP_PATH_INT8_MFMA or QAP_PATH_INT32 in
- * *delta_path, and 1 in *symmetric if F and D are both symmetric. */
+/* Path actually used by an instance: QAP_PATH_INT8_MFMA, QAP_PATH_SPLIT_MFMA
+ * or QAP_PATH_INT32 in *delta_path, and 1 in *symmetric if F and D are both
+ * symmetric. */
 int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric);
 
 /* Population statistics of the current goals of an instance (the percentile

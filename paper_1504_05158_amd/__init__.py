@@ -25,7 +25,7 @@ QAP_ERR_DEVICE = -4
 QAP_ERR_UNSUPPORTED = -5
 QAP_SV_RAW, QAP_SV_NORM = 0, 1
 QAP_INDEPENDENT, QAP_MIGRATION = 0, 1
-QAP_PATH_AUTO, QAP_PATH_INT8_MFMA, QAP_PATH_INT32 = 0, 1, 2
+QAP_PATH_AUTO, QAP_PATH_INT8_MFMA, QAP_PATH_INT32, QAP_PATH_SPLIT_MFMA = 0, 1, 2, 3
 QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
 
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
@@ -123,7 +123,7 @@ def _ptr(a: np.ndarray, ctype):
 
 
 _ENGINES = {"fused": QAP_ENGINE_FUSED, "plain": QAP_ENGINE_PLAIN}
-_PATHS = {"auto": QAP_PATH_AUTO, "int8": QAP_PATH_INT8_MFMA, "int32": QAP_PATH_INT32}
+_PATHS = {"auto": QAP_PATH_AUTO, "int8": QAP_PATH_INT8_MFMA, "int32": QAP_PATH_INT32, "split": QAP_PATH_SPLIT_MFMA}
 
 
 def make_params(*, num_swarms, particles_per_swarm, c1=0.8, c2=0.5, c3=0.5, vmax=1.0, norm=True, depth=2,
@@ -277,7 +277,7 @@ class Swarm:
         p = ctypes.c_int32()
         s = ctypes.c_int32()
         _check(load_library().qap_swarm_path(self.h, instance, ctypes.byref(p), ctypes.byref(s)), "qap_swarm_path")
-        return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32"}[p.value], bool(s.value)
+        return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32", QAP_PATH_SPLIT_MFMA: "split"}[p.value], bool(s.value)
 
     def graph_active(self) -> bool:
         """Whether stepping replays captured HIP graphs."""

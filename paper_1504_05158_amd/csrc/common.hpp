@@ -37,7 +37,8 @@ struct InstDesc {
     int migrate, migr_d, period;
     int sym;        // F and D both symmetric
     int zd;         // F and D both have a zero diagonal
-    int path;       // 1 int8 MFMA, 2 int32
+    int path;       // 1 int8 MFMA, 2 int32, 3 byte-split int8 MFMA
+    int split;      // path 3: bit 0 F split into two planes, bit 1 D split
     uint64_t seed;
     int swarm_base; // index of this descriptor's first swarm in the instance (random streams, records)
     // instance data
@@ -47,6 +48,10 @@ struct InstDesc {
     const int8_t* D8;       // [npad][npad] : D
     const int8_t* FT8;      // [npad][npad] : F^T
     const int8_t* DT8;      // [npad][npad] : D^T
+    // path 3: F8 / D8 hold the low planes (M mod 128 where split, else M),
+    // FH8 / DH8 the high planes floor(M / 128) of the split matrices
+    const int8_t* FH8;      // [npad][npad]
+    const int8_t* DH8;      // [npad][npad]
     // particle state; index [k] by particle, two buffers selected by iteration parity
     // V is kept column-scaled: V[r][c] = fl(U[r][c] * Vinv[c]) with U the
     // unnormalised S_v output and Vinv the reciprocal column norm (1 for raw

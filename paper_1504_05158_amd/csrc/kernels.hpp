@@ -26,20 +26,27 @@ hipError_t launch_bests(const InstDesc* descs, const int2* smap, int total_swarm
                         hipStream_t st);
 
 // Fused engine: one iteration of every instance of one kernel class (npad,
-// symmetric, zero diagonals) in one launch.  A class of one instance passes its
+// byte-split contraction, symmetric, zero diagonals) in one launch.  A class of one instance passes its
 // host descriptor `one` (a kernel argument); otherwise one = NULL and descs
 // [instances of the class] and blkmap [blocks] (workgroup -> (class-local
 // instance, first particle)) are device tables.  Bests follow separately.
-hipError_t launch_fused_class(int npad, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
+// wide: 0 int8, 1 byte-split with one matrix split, 2 both split.
+hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st);
 
 // Particles per workgroup of the fused kernel.
 constexpr int kFusedParticlesPerBlock = 4;
 
-// Whether the fused kernel covers an instance (int8 path, n <= 160).
+// Whether the fused kernel covers an instance (int8 path, or the byte-split
+// path with F and D symmetric; n <= 160; SecondTarget).
 bool fused_supported(const InstDesc& d);
 
-// Goal (+ deltas) of `count` permutations on the int8 MFMA path (eval only).
+// Whether the byte-split kernels cover a padded size and split pattern (bit 0
+// F split, bit 1 D split).
+bool split_supported(int npad, int split);
+
+// Goal (+ deltas) of `count` permutations on the int8 or byte-split MFMA path
+// (eval only).
 hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
                             long long* deltas, hipStream_t st);
 

@@ -364,31 +364,13 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
 }  // namespace
 
 // ------------------------------------------------------------------ fused step
-// TABLE: workgroup b steps particles blkmap[b].y .. +3 of instance
-// descs[blkmap[b].x]; otherwise workgroup b steps particles 4b .. 4b+3 of the
-// instance passed as `one` (a kernel argument, whose pointers the compiler
-// knows to be global: accesses through them avoid flat instructions).
-template <int NP, bool SYM, bool ZD, bool TABLE>
-__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
-                                                    const int2* __restrict__ blkmap)
+// Stages A and B of particle k (one wave): V(t+1) and its column scale
+// written, X(t+1) of SecondTarget (before the exchanges) left in pw, whose
+// entries n .. NP-1 are zeroed.  Returns the parity of the current buffers.
+template <int NP, int CPL>
+__device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uint8_t* pw, StLds<CPL>* sl)
 {
-    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
-    const InstDesc& d = TABLE ? descs[bm.x] : one;
-    constexpr int CPL = NP <= 64 ? 1 : NP <= 128 ? 2 : 4;  // column slots per lane
-    __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
-    __shared__ RowInfo sri[kWaves][NP];
-    __shared__ StLds<CPL> slds[kWaves];
-    load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
-    __syncthreads();
-
-    // wave index made explicitly uniform: every per-particle address lives in scalar registers
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave)), l = lane_id();
-    const int k = bm.y + w;
-    if (k >= d.P) return;
+    const int l = lane_id();
     const int n = d.n;
     const int tprev = *d.iter;
     const uint32_t tau = (uint32_t)tprev + 1u;
@@ -447,21 +429,27 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
     }
 
     // ---- B. SecondTarget
-    uint8_t* pw = sp[w];
     for (int j = n + l; j < NP; j += kWave) pw[j] = 0;
-    st_select<CPL>(n, d.depth, Vp, Sp, st, pw, &slds[w], d.seed, tau, s, g);
+    st_select<CPL>(n, d.depth, Vp, Sp, st, pw, sl, d.seed, tau, s, g);
     wave_sync();
+    return cur;
+}
 
-    // ---- C. goal, pair-exchange deltas, one exchange
-    // up to d.ls best-improvement exchanges: each one found while more are
-    // allowed is made in place and the deltas recomputed; the last allowed one
-    // is applied when X(t+1) is written
-    long long goal, key;
+// Stage C: up to d.ls best-improvement exchanges on pw.  contract(goal, key)
+// evaluates pw: its goal and the key (delta << 16 | a << 8 | b) of the first
+// minimum pair.  Each exchange found while more are allowed is made in place
+// and the deltas recomputed; the last allowed one is returned in (ba, bb), with
+// goal including it (ba = -1 if none).
+template <class Contract>
+__device__ __forceinline__ void exchanges(const InstDesc& d, uint8_t* pw, Contract contract, long long& goal,
+                                          int& ba, int& bb)
+{
+    long long key;
     int swaps = 0;
     for (;;) {
-        goal_delta_mfma<NP, SYM, ZD>(n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, goal, key);
+        contract(goal, key);
         if (d.ls <= swaps + 1 || key == LLONG_MAX || (key >> 16) >= 0) break;
-        if (l == 0) {
+        if (lane_id() == 0) {
             const int a = (int)((key >> 8) & 0xff), b = (int)(key & 0xff);
             const uint8_t t = pw[a];
             pw[a] = pw[b];
@@ -470,7 +458,8 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
         wave_sync();
         ++swaps;
     }
-    int ba = -1, bb = -1;
+    ba = -1;
+    bb = -1;
     if (d.ls > swaps && key != LLONG_MAX) {
         const long long del = key >> 16;
         if (del < 0) {
@@ -479,8 +468,13 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
             goal += del;
         }
     }
+}
 
-    // ---- D. X(t+1), goal, P^L
+// Stage D: X(t+1) (pw with a, b exchanged), goal, P^L.
+__device__ __forceinline__ void write_particle(const InstDesc& d, int k, int cur, const uint8_t* pw, long long goal,
+                                               int ba, int bb)
+{
+    const int n = d.n, l = lane_id();
     uint8_t* Xo = d.X[cur ^ 1] + (size_t)k * n;
     const bool improve = goal < d.goalPL[k];
     for (int j = l; j < n; j += kWave) {
@@ -494,6 +488,286 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
         d.goal[k] = goal;
         if (improve) d.goalPL[k] = goal;
     }
+}
+
+template <int NP>
+constexpr int cols_per_lane() { return NP <= 64 ? 1 : NP <= 128 ? 2 : 4; }
+
+// TABLE: workgroup b steps particles blkmap[b].y .. +3 of instance
+// descs[blkmap[b].x]; otherwise workgroup b steps particles 4b .. 4b+3 of the
+// instance passed as `one` (a kernel argument, whose pointers the compiler
+// knows to be global: accesses through them avoid flat instructions).
+template <int NP, bool SYM, bool ZD, bool TABLE>
+__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
+                                                    const int2* __restrict__ blkmap)
+{
+    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
+    const InstDesc& d = TABLE ? descs[bm.x] : one;
+    constexpr int CPL = cols_per_lane<NP>();  // column slots per lane
+    __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
+    __shared__ RowInfo sri[kWaves][NP];
+    __shared__ StLds<CPL> slds[kWaves];
+    load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
+    __syncthreads();
+
+    // wave index made explicitly uniform: every per-particle address lives in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int k = bm.y + w;
+    if (k >= d.P) return;
+    uint8_t* pw = sp[w];
+    const int cur = velocity_and_target<NP, CPL>(d, k, pw, &slds[w]);
+    long long goal;
+    int ba, bb;
+    exchanges(d, pw, [&](long long& g, long long& key) {
+        goal_delta_mfma<NP, SYM, ZD>(d.n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, g, key);
+    }, goal, ba, bb);
+    write_particle(d, k, cur, pw, goal, ba, bb);
+}
+
+// ------------------------------------------------------------------ wide step
+// Byte-split contraction for symmetric instances whose F or D leave the int8
+// range.  Each matrix M that needs it is split as M = 128 M_hi + M_lo with
+// M_lo in [0, 127] and M_hi = floor(M / 128) in [-128, 127] (|M| <= 16383); a
+// matrix that fits int8 keeps its value in the low plane.  Every product of
+// planes is an exact int8 MFMA, and the products are combined by Horner's rule
+// in int32: A = 128 (128 A_hh + A_hl + A_lh) + A_ll.
+//
+// Two equal ways to form A = F . Dp^T: (form 0) F rows direct from LDS and
+// Dp[y][k] = D[p_y][p_k] gathered; (form 1) D rows p_x direct and
+// Fq[y][l] = F[y][q_l] gathered, q = p^-1, since A[x][y] = sum_l F[x][q_l]
+// D[p_y][l].  The gathered operand is held in registers for every block; form
+// 1 is taken when only D is split, so that the held operand stays one plane.
+// HS (both matrices split) holds two planes: twice the registers.
+// For symmetric F and D the deltas use A_xy + A_yx only, which both forms
+// accumulate in one tile.
+
+// Row info of the wide path: f_xx, Dp_xx and the diagonal sum 2 A_xx.
+struct RowW {
+    short f, dp;
+    int da;
+};
+
+template <int NP, int CPL>
+struct WideWaveLds {
+    uint8_t p[NP];
+    uint8_t q[NP];
+    union {
+        StLds<CPL> st;   // stage B
+        RowW ri[NP];     // stage C
+    } u;
+};
+
+template <int NP>
+__device__ __forceinline__ void load_wide_lds(const InstDesc& d, int8_t* pl)
+{
+    constexpr int LS = lds_stride<NP>(), PS = NP * LS, RV = NP / 16;
+    const v4i* src[4] = {reinterpret_cast<const v4i*>(d.F8), reinterpret_cast<const v4i*>(d.FH8),
+                         reinterpret_cast<const v4i*>(d.D8), reinterpret_cast<const v4i*>(d.DH8)};
+    const bool on[4] = {true, (d.split & 1) != 0, true, (d.split & 2) != 0};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (!on[m]) continue;
+        for (int i = threadIdx.x; i < NP * RV; i += blockDim.x)
+            *reinterpret_cast<v4i*>(pl + m * PS + (i / RV) * LS + 16 * (i % RV)) = src[m][i];
+    }
+}
+
+// Entry off of a matrix from its low plane (and the high plane PS bytes on).
+template <int PS>
+__device__ __forceinline__ int wide_val(const int8_t* lo, int off, bool split)
+{
+    int v = lo[off];
+    if (split) v += 128 * (int)lo[off + PS];
+    return v;
+}
+
+// Stage C of the wide path for one permutation sp (NP bytes, zero beyond n);
+// sq receives q = p^-1 when form 1 is used.  Same results as goal_delta_mfma.
+// HS must equal (split == 3).
+template <int NP, bool ZD, bool HS>
+__device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_t* sp, uint8_t* sq, RowW* sri,
+                                bool want_pairs, long long* dout, long long& goal, long long& bestkey)
+{
+    constexpr int T = NP / 32, LS = lds_stride<NP>(), PS = NP * LS;
+    const int l = lane_id(), h = l >> 5, lc = l & 31;
+    const bool fs = HS || (split & 1) != 0, ds = HS || (split & 2) != 0;
+    const bool form = !HS && ds && !fs;
+    const int8_t* hl = pl + (form ? 0 : 2 * PS);  // held (gathered) operand, low plane
+    const int8_t* hh = hl + PS;
+    const int8_t* rl = pl + (form ? 2 * PS : 0);  // direct operand, low plane
+    const int8_t* rh = rl + PS;
+    constexpr bool hs = HS;
+    const bool rs = form || fs;
+    if (form) {
+        for (int j = l; j < NP; j += kWave) {
+            if (j < n) sq[sp[j]] = (uint8_t)j;
+            else sq[j] = 0;
+        }
+        wave_sync();
+    }
+    const uint8_t* idx = form ? sq : sp;
+    constexpr int TH = HS ? T : 1;
+    v4i Hl[T][T], Hh[TH][TH];
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+        const int y = 32 * b + lc;
+        const int gy = y < n ? (form ? y : (int)sp[y]) : 0;
+#pragma unroll
+        for (int kc = 0; kc < T; ++kc) {
+            Hl[b][kc] = y < n ? gather16<LS>(hl, gy, idx, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            if constexpr (HS) Hh[b][kc] = y < n ? gather16<LS>(hh, gy, idx, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+        }
+    }
+    // direct operand row of lane index x
+    auto drow = [&](int x) { return form ? (int)sp[x] : x; };
+    // diagonal tiles: A_xx -> row info; goal = trace(A) in 64 bits
+    long long gsum = 0;
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+        const int ra = drow(32 * a + lc);
+        v16i acc = {};
+        if constexpr (HS) {
+#pragma unroll
+            for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hh[a][kc], acc);
+            acc *= 128;
+        }
+        if (rs) {
+#pragma unroll
+            for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hl[a][kc], acc);
+        }
+        if constexpr (HS) {
+#pragma unroll
+            for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hh[a][kc], acc);
+        }
+        if (rs || hs) acc *= 128;
+#pragma unroll
+        for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hl[a][kc], acc);
+        if (h == ((lc >> 2) & 1)) {
+            const int want = 4 * (lc >> 3) + (lc & 3);
+            int da = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i == want) da = acc[i];
+            const int x = 32 * a + lc;
+            if (x < n) {
+                gsum += da;
+                const int px = sp[x];
+                RowW ri;
+                ri.f = (short)wide_val<PS>(pl, x * LS + x, fs);
+                ri.dp = (short)wide_val<PS>(pl + 2 * PS, px * LS + px, ds);
+                ri.da = 2 * da;
+                sri[x] = ri;
+            }
+        }
+    }
+    goal = wave_sum_i64(gsum);
+    bestkey = LLONG_MAX;
+    if (!want_pairs) return;
+    wave_sync();
+#pragma unroll
+    for (int a = 0; a < T; ++a) {
+#pragma unroll
+        for (int b = a; b < T; ++b) {
+            const int y = 32 * b + lc;
+            const int ra = drow(32 * a + lc), rb = drow(y);
+            // acc = A + A^T on the tile (x in block a, y in block b)
+            v16i acc = {};
+            if constexpr (HS) {
+#pragma unroll
+                for (int kc = 0; kc < T; ++kc) {
+                    acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hh[b][kc], acc);
+                    acc = mfma32(Hh[a][kc], frag16<LS>(rh, rb, 32 * kc + 16 * h), acc);
+                }
+                acc *= 128;
+            }
+            if (rs) {
+#pragma unroll
+                for (int kc = 0; kc < T; ++kc) {
+                    acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hl[b][kc], acc);
+                    acc = mfma32(Hl[a][kc], frag16<LS>(rh, rb, 32 * kc + 16 * h), acc);
+                }
+            }
+            if constexpr (HS) {
+#pragma unroll
+                for (int kc = 0; kc < T; ++kc) {
+                    acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hh[b][kc], acc);
+                    acc = mfma32(Hh[a][kc], frag16<LS>(rl, rb, 32 * kc + 16 * h), acc);
+                }
+            }
+            if (rs || hs) acc *= 128;
+#pragma unroll
+            for (int kc = 0; kc < T; ++kc) {
+                acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hl[b][kc], acc);
+                acc = mfma32(Hl[a][kc], frag16<LS>(rl, rb, 32 * kc + 16 * h), acc);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (y >= n) continue;
+            const RowW cy = sri[y];
+            const int py = sp[y];
+            int tmin = INT_MAX, ti = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int xo = 8 * (i >> 2) + (i & 3);
+                const int x = 32 * a + 4 * h + xo;
+                if (a == b && x >= y) continue;  // diagonal tiles: x < y only
+                const RowW rx = sri[x];
+                const int px = sp[x];
+                const int fxy = wide_val<PS>(pl, x * LS + y, fs);
+                const int dxy = wide_val<PS>(pl + 2 * PS, px * LS + py, ds);
+                const int base = 2 * acc[i] - rx.da - cy.da;
+                int del;
+                if constexpr (ZD)
+                    del = base + 4 * fxy * dxy;
+                else
+                    del = base + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
+                if (dout) {
+                    dout[(size_t)x * n + y] = del;
+                    dout[(size_t)y * n + x] = del;
+                }
+                const bool lt = del < tmin;
+                tmin = lt ? del : tmin;
+                ti = lt ? i : ti;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (tmin != INT_MAX) {
+                const int x = 32 * a + 4 * h + 8 * (ti >> 2) + (ti & 3);
+                const long long key = ((long long)tmin << 16) | (x << 8) | y;
+                bestkey = key < bestkey ? key : bestkey;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    bestkey = wave_min_i64(bestkey);
+}
+
+template <int NP, bool ZD, bool HS, bool TABLE>
+__global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
+                                                    const int2* __restrict__ blkmap)
+{
+    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
+    const InstDesc& d = TABLE ? descs[bm.x] : one;
+    constexpr int CPL = cols_per_lane<NP>();
+    __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[kWaves];
+    load_wide_lds<NP>(d, spl);
+    __syncthreads();
+
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int k = bm.y + w;
+    if (k >= d.P) return;
+    uint8_t* pw = sw[w].p;
+    const int cur = velocity_and_target<NP, CPL>(d, k, pw, &sw[w].u.st);
+    wave_sync();  // stage B's scratch is reused for the row info
+    long long goal;
+    int ba, bb;
+    exchanges(d, pw, [&](long long& g, long long& key) {
+        goal_delta_wide<NP, ZD, HS>(d.n, d.split, spl, pw, sw[w].q, sw[w].u.ri, d.ls != 0, nullptr, g, key);
+    }, goal, ba, bb);
+    write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
 // ------------------------------------------------------------------ eval
@@ -524,58 +798,118 @@ __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __
     if (l == 0) goals[e] = goal;
 }
 
+template <int NP, bool ZD, bool HS>
+__global__ __launch_bounds__(256) void k_eval_wide(InstDesc d, const uint8_t* __restrict__ perms, int count,
+                                                   long long* __restrict__ goals, long long* __restrict__ deltas)
+{
+    constexpr int CPL = cols_per_lane<NP>();
+    __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[kWaves];
+    load_wide_lds<NP>(d, spl);
+    __syncthreads();
+    const int w = threadIdx.x / kWave, l = lane_id();
+    const int e = blockIdx.x * kWaves + w;
+    if (e >= count) return;
+    const int n = d.n;
+    uint8_t* pw = sw[w].p;
+    for (int j = l; j < NP; j += kWave) pw[j] = j < n ? perms[(size_t)e * n + j] : 0;
+    wave_sync();
+    long long* dout = deltas ? deltas + (size_t)e * n * n : nullptr;
+    long long goal, key;
+    goal_delta_wide<NP, ZD, HS>(n, d.split, spl, pw, sw[w].q, sw[w].u.ri, dout != nullptr, dout, goal, key);
+    if (dout)
+        for (int j = l; j < n; j += kWave) dout[(size_t)j * n + j] = 0;
+    if (l == 0) goals[e] = goal;
+}
+
 // ------------------------------------------------------------------ launchers
-// Contraction variants: general (F or D not symmetric), symmetric, symmetric
-// with zero diagonals.
-template <int NP, bool SYM, bool ZD>
+// Contraction variants: int8 general (F or D not symmetric), int8 symmetric,
+// int8 symmetric with zero diagonals, and the byte-split symmetric ones (WIDE 1:
+// one matrix split, 2: both; both split at npad 160 would not fit the register
+// file and is left to the int32 path).
+template <int NP, int WIDE, bool SYM, bool ZD>
 static hipError_t fused_launch_one(const InstDesc* one, const InstDesc* descs, const int2* blkmap, int blocks,
                                    hipStream_t st)
 {
     const dim3 grid((unsigned)blocks), block(kWaves * kWave);
-    if (one)
-        hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, false>), grid, block, 0, st, *one, descs, blkmap);
-    else
-        hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
+    if constexpr (WIDE == 2 && NP > 128) {
+        return hipErrorNotSupported;
+    } else if constexpr (WIDE != 0) {
+        if (one)
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, false>), grid, block, 0, st, *one, descs, blkmap);
+        else
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
+    } else {
+        if (one)
+            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, false>), grid, block, 0, st, *one, descs, blkmap);
+        else
+            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
+    }
     return hipGetLastError();
 }
 
-template <bool SYM, bool ZD>
+template <int WIDE, bool SYM, bool ZD>
 static hipError_t fused_launch_np(int npad, const InstDesc* one, const InstDesc* descs, const int2* blkmap,
                                   int blocks, hipStream_t st)
 {
     switch (npad) {
-    case 32: return fused_launch_one<32, SYM, ZD>(one, descs, blkmap, blocks, st);
-    case 64: return fused_launch_one<64, SYM, ZD>(one, descs, blkmap, blocks, st);
-    case 96: return fused_launch_one<96, SYM, ZD>(one, descs, blkmap, blocks, st);
-    case 128: return fused_launch_one<128, SYM, ZD>(one, descs, blkmap, blocks, st);
-    case 160: return fused_launch_one<160, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 32: return fused_launch_one<32, WIDE, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 64: return fused_launch_one<64, WIDE, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 96: return fused_launch_one<96, WIDE, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 128: return fused_launch_one<128, WIDE, SYM, ZD>(one, descs, blkmap, blocks, st);
+    case 160: return fused_launch_one<160, WIDE, SYM, ZD>(one, descs, blkmap, blocks, st);
     default: return hipErrorNotSupported;
     }
 }
 
-bool fused_supported(const InstDesc& d) { return d.path == 1 && d.npad <= 160 && d.sx == 0; }
+bool split_supported(int npad, int split) { return npad <= 160 && (split != 3 || npad <= 128); }
 
-hipError_t launch_fused_class(int npad, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
+bool fused_supported(const InstDesc& d)
+{
+    return (d.path == 1 || (d.path == 3 && d.sym && split_supported(d.npad, d.split))) && d.npad <= 160 && d.sx == 0;
+}
+
+hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st)
 {
     static_assert(kWaves == kFusedParticlesPerBlock, "one wave per particle");
     if (blocks <= 0) return hipSuccess;
-    return !sym ? fused_launch_np<false, false>(npad, one, descs, blkmap, blocks, st)
-                : zd ? fused_launch_np<true, true>(npad, one, descs, blkmap, blocks, st)
-                     : fused_launch_np<true, false>(npad, one, descs, blkmap, blocks, st);
+    if (wide == 1)
+        return !sym ? hipErrorNotSupported
+                    : zd ? fused_launch_np<1, true, true>(npad, one, descs, blkmap, blocks, st)
+                         : fused_launch_np<1, true, false>(npad, one, descs, blkmap, blocks, st);
+    if (wide == 2)
+        return !sym ? hipErrorNotSupported
+                    : zd ? fused_launch_np<2, true, true>(npad, one, descs, blkmap, blocks, st)
+                         : fused_launch_np<2, true, false>(npad, one, descs, blkmap, blocks, st);
+    return !sym ? fused_launch_np<0, false, false>(npad, one, descs, blkmap, blocks, st)
+                : zd ? fused_launch_np<0, true, true>(npad, one, descs, blkmap, blocks, st)
+                     : fused_launch_np<0, true, false>(npad, one, descs, blkmap, blocks, st);
 }
 
-template <bool SYM, bool ZD>
+template <int NP, int WIDE, bool SYM, bool ZD>
+static void eval_launch_one(const InstDesc& d, const uint8_t* perms, int count, long long* goals, long long* deltas,
+                            hipStream_t st)
+{
+    const dim3 grid((unsigned)((count + kWaves - 1) / kWaves)), block(kWaves * kWave);
+    if constexpr (WIDE == 2 && NP > 128)
+        return;  // not reached: split_supported
+    else if constexpr (WIDE != 0)
+        hipLaunchKernelGGL((k_eval_wide<NP, ZD, WIDE == 2>), grid, block, 0, st, d, perms, count, goals, deltas);
+    else
+        hipLaunchKernelGGL((k_eval_mfma<NP, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas);
+}
+
+template <int WIDE, bool SYM, bool ZD>
 static hipError_t eval_launch_np(const InstDesc& d, const uint8_t* perms, int count, long long* goals,
                                  long long* deltas, hipStream_t st)
 {
-    const dim3 grid((unsigned)((count + kWaves - 1) / kWaves)), block(kWaves * kWave);
     switch (d.npad) {
-    case 32: hipLaunchKernelGGL((k_eval_mfma<32, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 64: hipLaunchKernelGGL((k_eval_mfma<64, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 96: hipLaunchKernelGGL((k_eval_mfma<96, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 128: hipLaunchKernelGGL((k_eval_mfma<128, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
-    case 160: hipLaunchKernelGGL((k_eval_mfma<160, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas); break;
+    case 32: eval_launch_one<32, WIDE, SYM, ZD>(d, perms, count, goals, deltas, st); break;
+    case 64: eval_launch_one<64, WIDE, SYM, ZD>(d, perms, count, goals, deltas, st); break;
+    case 96: eval_launch_one<96, WIDE, SYM, ZD>(d, perms, count, goals, deltas, st); break;
+    case 128: eval_launch_one<128, WIDE, SYM, ZD>(d, perms, count, goals, deltas, st); break;
+    case 160: eval_launch_one<160, WIDE, SYM, ZD>(d, perms, count, goals, deltas, st); break;
     default: return hipErrorNotSupported;
     }
     return hipGetLastError();
@@ -585,9 +919,17 @@ hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, 
                             hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
-    return !d.sym ? eval_launch_np<false, false>(d, perms, count, goals, deltas, st)
-                  : d.zd ? eval_launch_np<true, true>(d, perms, count, goals, deltas, st)
-                         : eval_launch_np<true, false>(d, perms, count, goals, deltas, st);
+    if (d.path == 3) {
+        if (!d.sym || !split_supported(d.npad, d.split)) return hipErrorNotSupported;
+        if (d.split == 3)
+            return d.zd ? eval_launch_np<2, true, true>(d, perms, count, goals, deltas, st)
+                        : eval_launch_np<2, true, false>(d, perms, count, goals, deltas, st);
+        return d.zd ? eval_launch_np<1, true, true>(d, perms, count, goals, deltas, st)
+                    : eval_launch_np<1, true, false>(d, perms, count, goals, deltas, st);
+    }
+    return !d.sym ? eval_launch_np<0, false, false>(d, perms, count, goals, deltas, st)
+                  : d.zd ? eval_launch_np<0, true, true>(d, perms, count, goals, deltas, st)
+                         : eval_launch_np<0, true, false>(d, perms, count, goals, deltas, st);
 }
 
 }  // namespace qap

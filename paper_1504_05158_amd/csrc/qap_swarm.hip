@@ -41,6 +41,7 @@ struct Instance {
 // symmetric, zero diagonals) its descriptors and workgroup map.
 struct FusedClass {
     int npad = 0;
+    int wide = 0;  // 0 int8, 1 byte-split (one matrix split), 2 both split
     bool sym = false, zd = false;
     int blocks = 0;
     qap::InstDesc* descs = nullptr;  // device [instances of the class]
@@ -129,7 +130,7 @@ int check_params(const qap_instance* in, const qap_params* p)
         if (2 * d >= p->num_swarms && d > 0) return QAP_ERR_INVALID_ARG;
     }
     if (p->local_search < 0 || p->local_search > QAP_MAX_EXCHANGES) return QAP_ERR_INVALID_ARG;
-    if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_INT32) return QAP_ERR_INVALID_ARG;
+    if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_SPLIT_MFMA) return QAP_ERR_INVALID_ARG;
     if (p->engine != QAP_ENGINE_FUSED && p->engine != QAP_ENGINE_PLAIN) return QAP_ERR_INVALID_ARG;
     if (p->stream_groups < 0 || p->stream_groups > kStreamGroups) return QAP_ERR_INVALID_ARG;
     if (p->sx_procedure != QAP_SX_SECOND_TARGET && p->sx_procedure != QAP_SX_PICK_COLUMN) return QAP_ERR_INVALID_ARG;
@@ -137,13 +138,17 @@ int check_params(const qap_instance* in, const qap_params* p)
 }
 
 // Range check and path choice.  int8 MFMA needs every entry in [-128, 127];
-// any exact int32 contraction needs n * max|F| * max|D| < 2^31.
+// any exact int32 contraction needs n * max|F| * max|D| < 2^31.  The
+// byte-split MFMA path needs F and D symmetric, every entry in
+// [-16384, 16383] (two planes of 7 + 8 bits) and 8 (n + 3) max|F| max|D| <
+// 2^31, which bounds every delta (at most 8 (n + 2) max|F| max|D| in size) and
+// every partial sum of its int32 epilogue.
 int choose_path(const qap_instance* in, const qap_params* p, int engine, int* path, int* sym, int* mul24,
-                int* zd)
+                int* zd, int* split)
 {
     const int n = in->n;
     long long mf = 0, md = 0;
-    bool f8 = true, s = true, z = true;
+    bool f8 = true, s = true, z = true, fs = false, ds = false, w15 = true;
     for (int i = 0; i < n; ++i) z = z && in->F[i * n + i] == 0 && in->D[i * n + i] == 0;
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j) {
@@ -151,29 +156,39 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
             mf = std::max(mf, f < 0 ? -f : f);
             md = std::max(md, dd < 0 ? -dd : dd);
             if (f < -128 || f > 127 || dd < -128 || dd > 127) f8 = false;
+            fs = fs || f < -128 || f > 127;
+            ds = ds || dd < -128 || dd > 127;
+            w15 = w15 && f >= -16384 && f <= 16383 && dd >= -16384 && dd <= 16383;
             if (in->F[i * n + j] != in->F[j * n + i] || in->D[i * n + j] != in->D[j * n + i]) s = false;
         }
     if ((long long)n * mf * md >= (1LL << 31)) return QAP_ERR_RANGE;
+    const bool fused = engine == QAP_ENGINE_FUSED && n <= 160 && p->sx_procedure == QAP_SX_SECOND_TARGET;
+    const int spl = (fs ? 1 : 0) | (ds ? 2 : 0);
+    const bool split_ok = s && w15 && 8LL * (n + 3) * mf * md < (1LL << 31) &&
+                          qap::split_supported((n + 31) / 32 * 32, spl);
     int pth;
     if (p->delta_path == QAP_PATH_INT8_MFMA) {
         if (!f8) return QAP_ERR_RANGE;
         pth = 1;
+    } else if (p->delta_path == QAP_PATH_SPLIT_MFMA) {
+        if (!split_ok) return QAP_ERR_RANGE;
+        pth = 3;
     } else if (p->delta_path == QAP_PATH_INT32) {
         pth = 2;
     } else {
-        pth = f8 ? 1 : 2;
+        pth = f8 ? 1 : split_ok && fused ? 3 : 2;
     }
-    if (engine == QAP_ENGINE_PLAIN || n > 160 || p->sx_procedure == QAP_SX_PICK_COLUMN)
-        pth = 2;  // the fused kernel covers SecondTarget with n <= 160
+    if (!fused) pth = 2;  // the fused kernels cover SecondTarget with n <= 160
     *path = pth;
     *sym = s ? 1 : 0;
     *mul24 = (mf < (1LL << 23) && md < (1LL << 23)) ? 1 : 0;
     *zd = z ? 1 : 0;
+    *split = pth == 3 ? spl : 0;
     return QAP_OK;
 }
 
 int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_params* p, int path, int sym,
-                   int mul24, int zd)
+                   int mul24, int zd, int split)
 {
     const int n = in->n;
     InstDesc& d = I.d;
@@ -198,6 +213,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     d.sym = sym;
     d.zd = zd;
     d.path = path;
+    d.split = split;
     d.seed = p->seed;
     const size_t nn = (size_t)n * n, P = (size_t)I.P;
     hipError_t e = hipSuccess;
@@ -228,6 +244,33 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
         TRY(hipMemcpy(FT8, hFT.data(), np * np, hipMemcpyHostToDevice));
         TRY(hipMemcpy(DT8, hDT.data(), np * np, hipMemcpyHostToDevice));
         d.F8 = F8; d.D8 = D8; d.FT8 = FT8; d.DT8 = DT8;
+    } else if (path == 3) {
+        // planes of F and D (both symmetric): low = M mod 128 and high =
+        // floor(M / 128) for a split matrix, low = M otherwise
+        const size_t np = (size_t)d.npad;
+        const int* src[2] = {in->F, in->D};
+        const int8_t** lo[2] = {&d.F8, &d.D8};
+        const int8_t** hi[2] = {&d.FH8, &d.DH8};
+        for (int m = 0; m < 2; ++m) {
+            const bool sp = (split >> m) & 1;
+            std::vector<int8_t> hl(np * np, 0), hh(np * np, 0);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    const int v = src[m][i * n + j];
+                    const int low = sp ? (v & 127) : v;
+                    hl[i * np + j] = (int8_t)low;
+                    hh[i * np + j] = (int8_t)((v - low) / 128);
+                }
+            int8_t *L, *H = nullptr;
+            TRY(dalloc(I, &L, np * np));
+            TRY(hipMemcpy(L, hl.data(), np * np, hipMemcpyHostToDevice));
+            if (sp) {
+                TRY(dalloc(I, &H, np * np));
+                TRY(hipMemcpy(H, hh.data(), np * np, hipMemcpyHostToDevice));
+            }
+            *lo[m] = L;
+            *hi[m] = H;
+        }
     }
     TRY(dalloc(I, &d.V[0], P * nn));
     TRY(dalloc(I, &d.V[1], P * nn));
@@ -312,6 +355,8 @@ void free_plan(StepPlan& pl)
     pl = StepPlan();
 }
 
+int fused_kind(const qap::InstDesc& d) { return d.path != 3 ? 0 : d.split == 3 ? 2 : 1; }
+
 // Device tables of one step over the descriptors descs (entry i belongs to
 // instance owner[i]); instances whose entry is not on the fused kernel go to
 // the per-stage list.
@@ -336,11 +381,13 @@ int build_plan(qap_swarm* h, StepPlan& pl, const std::vector<qap::InstDesc>& all
         }
         size_t c = 0;
         while (c < pl.fused.size() &&
-               !(pl.fused[c].npad == d.npad && pl.fused[c].sym == (d.sym != 0) && pl.fused[c].zd == (d.zd != 0)))
+               !(pl.fused[c].npad == d.npad && pl.fused[c].wide == fused_kind(d) && pl.fused[c].sym == (d.sym != 0) &&
+                 pl.fused[c].zd == (d.zd != 0)))
             ++c;
         if (c == pl.fused.size()) {
             FusedClass fc;
             fc.npad = d.npad;
+            fc.wide = fused_kind(d);
             fc.sym = d.sym != 0;
             fc.zd = d.zd != 0;
             pl.fused.push_back(fc);
@@ -493,7 +540,7 @@ int enqueue_iteration(qap_swarm* h, int j)
     if (!pl.fused.empty()) {
         REC(2 * QAP_STAGE_FUSED);
         for (const FusedClass& fc : pl.fused) {
-            e = qap::launch_fused_class(fc.npad, fc.sym, fc.zd, fc.host.size() == 1 ? &fc.host[0] : nullptr,
+            e = qap::launch_fused_class(fc.npad, fc.wide, fc.sym, fc.zd, fc.host.size() == 1 ? &fc.host[0] : nullptr,
                                         fc.descs, fc.blkmap, fc.blocks, st);
             if (e != hipSuccess) return dev_err(h, e);
         }
@@ -599,13 +646,14 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     *out = nullptr;
     if (!insts || !prms || count < 1) return QAP_ERR_INVALID_ARG;
     // every host-side check comes before the first HIP call
-    std::vector<int> path((size_t)count), sym((size_t)count), mul24((size_t)count), zd((size_t)count);
+    std::vector<int> path((size_t)count), sym((size_t)count), mul24((size_t)count), zd((size_t)count),
+        split((size_t)count);
     for (int k = 0; k < count; ++k) {
         int rc = check_params(&insts[k], &prms[k]);
         if (rc != QAP_OK) return rc;
         if (prms[k].engine != prms[0].engine) return QAP_ERR_INVALID_ARG;
         rc = choose_path(&insts[k], &prms[k], prms[0].engine, &path[(size_t)k], &sym[(size_t)k], &mul24[(size_t)k],
-                         &zd[(size_t)k]);
+                         &zd[(size_t)k], &split[(size_t)k]);
         if (rc != QAP_OK) return rc;
     }
     qap_swarm* h = new (std::nothrow) qap_swarm();
@@ -624,7 +672,7 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     h->inst.resize((size_t)count);
     for (int k = 0; k < count; ++k) {
         const int rc = setup_instance(h, h->inst[(size_t)k], &insts[k], &prms[k], path[(size_t)k], sym[(size_t)k],
-                                      mul24[(size_t)k], zd[(size_t)k]);
+                                      mul24[(size_t)k], zd[(size_t)k], split[(size_t)k]);
         if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
     }
     int rc = build_plans(h);
@@ -860,7 +908,7 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
     if (e == hipSuccess && deltas) e = hipMalloc(&dd, sizeof(long long) * (size_t)count * n * n);
     if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
-        if (I->d.path == 1 && qap::fused_supported(I->d))
+        if (qap::fused_supported(I->d))
             e = qap::launch_eval_mfma(I->d, dp, count, dg, dd, h->stream);
         else
             e = qap::launch_goal_delta_i32(I->d, I->mul24, h->grid_gd, dp, count, 1, dg, dd, h->stream);
@@ -978,7 +1026,8 @@ int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t*
     Instance* I;
     int rc = get_instance(h, instance, &I);
     if (rc != QAP_OK) return rc;
-    if (delta_path) *delta_path = I->d.path == 1 ? QAP_PATH_INT8_MFMA : QAP_PATH_INT32;
+    if (delta_path)
+        *delta_path = I->d.path == 1 ? QAP_PATH_INT8_MFMA : I->d.path == 3 ? QAP_PATH_SPLIT_MFMA : QAP_PATH_INT32;
     if (symmetric) *symmetric = I->d.sym;
     return QAP_OK;
 }

@@ -25,7 +25,8 @@ def assert_same(a, b, what):
 def mixed_cases():
     """Mixed sizes and kinds: symmetric zero-diagonal int8 instances of several
     padded sizes, a symmetric one with non-zero diagonals, a general one, one
-    too wide for int8 (int32 per-stage kernels), and one in migration mode."""
+    too wide for int8 (byte-split on the fused engine), an asymmetric wide one
+    (int32 per-stage kernels), and one in migration mode."""
     cases = []
     for i, (F, D) in enumerate(gen.mixed_batch(count=5, seed=105, lo_n=12, hi_n=150)):
         cases.append((F, D, run_cfg(num_swarms=2 + i % 2, particles_per_swarm=8 + 3 * i, seed=10 + i)))
@@ -36,7 +37,9 @@ def mixed_cases():
     F, D = gen.general_instance(33, -20, 40, 5)
     cases.append((F, D, run_cfg(seed=22)))                                   # general
     F, D = gen.uniform_instance(50, 0, 1000, 9)
-    cases.append((F, D, run_cfg(seed=23, depth=1)))                          # int32 path
+    cases.append((F, D, run_cfg(seed=23, depth=1)))                          # byte-split path (fused engine)
+    F, D = gen.general_instance(36, -900, 900, 6)
+    cases.append((F, D, run_cfg(seed=25)))                                   # int32 path (asymmetric, wide)
     F, D = gen.uniform_instance(64, 0, 99, 11)
     cases.append((F, D, run_cfg(num_swarms=6, particles_per_swarm=5, migration=True, migration_factor=0.34,
                                 migration_period=2, seed=24)))              # migration
