@@ -80,7 +80,8 @@ __device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c)
 // acc element i of lane l in a 32x32 tile: row 8(i/4) + 4(l/32) + i%4, column l%32
 __device__ __forceinline__ int tile_row(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
 
-// Row info per index x: p_x, f_xx, Dp_xx, diagonal sum dA_x (A_xx, or A_xx + B_xx).
+// Row info per index x: p_x, f_xx, Dp_xx, diagonal term dA_x (A_xx when F and
+// D are symmetric, else A_xx + B_xx).
 struct RowInfo {
     int p, f, dp, da;
 };
@@ -135,7 +136,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 ri.p = px;
                 ri.f = sF[x * LS + x];
                 ri.dp = sD[px * LS + px];
-                ri.da = SYM ? 2 * da : da + db;
+                ri.da = SYM ? da : da + db;
                 sri[x] = ri;
             }
         }
@@ -150,13 +151,17 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
 #pragma unroll
         for (int b = a; b < T; ++b) {
             const int y = 32 * b + lc;
+            // symmetric F, D: A holds A + A^T on the tile (the deltas need only the sum)
             v16i A = {}, AT = {}, B = {}, BT = {};
 #pragma unroll
             for (int kc = 0; kc < T; ++kc) {
                 const v4i fa = frag16<LS>(sF, 32 * a + lc, 32 * kc + 16 * h);
                 const v4i fb = frag16<LS>(sF, 32 * b + lc, 32 * kc + 16 * h);
-                A = mfma32(fa, dp[b][kc], A);     // A[x][y]  = sum_k F[x][k] Dp[y][k]
-                AT = mfma32(dp[a][kc], fb, AT);   // AT[x][y] = sum_k Dp[x][k] F[y][k] = A[y][x]
+                A = mfma32(fa, dp[b][kc], A);            // A[x][y]  = sum_k F[x][k] Dp[y][k]
+                if constexpr (SYM)
+                    A = mfma32(dp[a][kc], fb, A);        // + A^T[x][y] = sum_k Dp[x][k] F[y][k] = A[y][x]
+                else
+                    AT = mfma32(dp[a][kc], fb, AT);
                 if constexpr (!SYM) {
                     const v4i ga = frag16<LS>(sFT, 32 * a + lc, 32 * kc + 16 * h);
                     const v4i gb = frag16<LS>(sFT, 32 * b + lc, 32 * kc + 16 * h);
@@ -172,7 +177,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             const RowInfo* rxb = sri + 32 * a + 4 * h;
             const int8_t* fxb = sF + (32 * a + 4 * h) * LS + y;
             const int8_t* fyb = sF + y * LS + 32 * a + 4 * h;
-            const int8_t* dyb = sD + cy.p;
+            // ZD: the minimum is taken over hdel = (A_xy + A_yx - A_xx) + 2 f_xy Dp_xy,
+            // delta = 2 (hdel - A_yy): increasing in hdel, so the same first minimum
             int tmin = INT_MAX, ti = 0;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -180,17 +186,15 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 if (a == b && 32 * a + 4 * h + xo >= y) continue;  // diagonal tiles: x < y only
                 const RowInfo rx = rxb[xo];
                 const int fxy = fxb[xo * LS];
-                const int dxy = dyb[rx.p * LS];
+                const int dxy = sD[__umul24(rx.p, LS) + cy.p];  // 24-bit multiply: p < 256
                 int del;
-                if constexpr (SYM) {
-                    const int base = 2 * (A[i] + AT[i]) - rx.da - cy.da;
-                    if constexpr (ZD)
-                        del = base + 4 * fxy * dxy;
-                    else
-                        del = base + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
+                if constexpr (SYM && ZD) {
+                    del = A[i] - rx.da + 2 * fxy * dxy;
+                } else if constexpr (SYM) {
+                    del = 2 * (A[i] - rx.da - cy.da) + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
                 } else {
                     const int fyx = fyb[xo];
-                    const int dyx = sD[cy.p * LS + rx.p];
+                    const int dyx = sD[__umul24(cy.p, LS) + rx.p];
                     const int faa = rx.f, fbb = cy.f, daa = rx.dp, dbb = cy.dp;
                     const int kap = (faa - fyx) * (dyx - daa) + (fxy - fbb) * (dbb - dxy) + (faa - fxy) * (dxy - daa) +
                                     (fyx - fbb) * (dbb - dyx);
@@ -199,8 +203,9 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 }
                 if (dout) {
                     const int x = 32 * a + 4 * h + xo;
-                    dout[(size_t)x * n + y] = del;
-                    dout[(size_t)y * n + x] = del;
+                    const int full = (SYM && ZD) ? 2 * (del - cy.da) : del;
+                    dout[(size_t)x * n + y] = full;
+                    dout[(size_t)y * n + x] = full;
                 }
                 const bool lt = del < tmin;
                 tmin = lt ? del : tmin;
@@ -208,6 +213,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (tmin != INT_MAX) {
+                if constexpr (SYM && ZD) tmin = 2 * (tmin - cy.da);
                 // (delta, x, y) as one ordered 64-bit key: delta * 2^16 + x * 2^8 + y
                 const int x = 32 * a + 4 * h + 8 * (ti >> 2) + (ti & 3);
                 const long long key = ((long long)tmin << 16) | (x << 8) | y;
@@ -275,22 +281,27 @@ __device__ __forceinline__ void fix_cells(__amdgpu_buffer_rsrc_t rq, uint32_t co
 {
     if (at.xr >= lo && at.xr < hi) {
         const float x = __fmul_rn(ex, sc);
-        const float t = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), __fmul_rn(s2, at.ax)), __fmul_rn(s3, at.bx)), vmax);
-        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
-        bstore(rq, col + (uint32_t)at.xr * rowb, 0u, t);
         vx = x;
+        // rows of X, P^L and P^G all equal: both terms vanish and the plain
+        // value stands (a re-store would cost a partial write of its line)
+        if (at.ax != 0.0f || at.bx != 0.0f) {
+            const float t =
+                clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), __fmul_rn(s2, at.ax)), __fmul_rn(s3, at.bx)), vmax);
+            sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+            bstore(rq, col + __umul24(at.xr, rowb), 0u, t);
+        }
     }
     if (at.lr != at.xr && at.lr >= lo && at.lr < hi) {
         const float x = __fmul_rn(el, sc);
         const float t = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), s2), __fmul_rn(s3, at.bl)), vmax);
         sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
-        bstore(rq, col + (uint32_t)at.lr * rowb, 0u, t);
+        bstore(rq, col + __umul24(at.lr, rowb), 0u, t);
     }
     if (at.gr != at.xr && at.gr != at.lr && at.gr >= lo && at.gr < hi) {
         const float x = __fmul_rn(eg, sc);
         const float t = clampv(__fadd_rn(__fmul_rn(c1, x), s3), vmax);
         sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
-        bstore(rq, col + (uint32_t)at.gr * rowb, 0u, t);
+        bstore(rq, col + __umul24(at.gr, rowb), 0u, t);
     }
 }
 
@@ -325,9 +336,9 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
         for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)(r0 + u) * rowb);
         // attraction rows of this batch (row r0 stands in for absent ones: same lines)
         const int hi = r0 + B;
-        const float ex = bload(rp, col + (uint32_t)(at.xr >= r0 && at.xr < hi ? at.xr : r0) * rowb, 0u);
-        const float el = bload(rp, col + (uint32_t)(at.lr >= r0 && at.lr < hi ? at.lr : r0) * rowb, 0u);
-        const float eg = bload(rp, col + (uint32_t)(at.gr >= r0 && at.gr < hi ? at.gr : r0) * rowb, 0u);
+        const float ex = bload(rp, col + __umul24(at.xr >= r0 && at.xr < hi ? at.xr : r0, rowb), 0u);
+        const float el = bload(rp, col + __umul24(at.lr >= r0 && at.lr < hi ? at.lr : r0, rowb), 0u);
+        const float eg = bload(rp, col + __umul24(at.gr >= r0 && at.gr < hi ? at.gr : r0, rowb), 0u);
         const float mb = m1;
         int u1 = 0;
 #pragma unroll
@@ -353,9 +364,9 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
         bstore(rq, col, (uint32_t)r * rowb, t);
     }
     if (lo < n) {
-        const float ex = bload(rp, col + (uint32_t)(at.xr >= lo ? at.xr : lo) * rowb, 0u);
-        const float el = bload(rp, col + (uint32_t)(at.lr >= lo ? at.lr : lo) * rowb, 0u);
-        const float eg = bload(rp, col + (uint32_t)(at.gr >= lo ? at.gr : lo) * rowb, 0u);
+        const float ex = bload(rp, col + __umul24(at.xr >= lo ? at.xr : lo, rowb), 0u);
+        const float el = bload(rp, col + __umul24(at.lr >= lo ? at.lr : lo, rowb), 0u);
+        const float eg = bload(rp, col + __umul24(at.gr >= lo ? at.gr : lo, rowb), 0u);
         fix_cells(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s2, s3, vmax, sum, vx);
     }
     return sum;
@@ -717,7 +728,7 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                 const RowW rx = sri[x];
                 const int px = sp[x];
                 const int fxy = wide_val<PS>(pl, x * LS + y, fs);
-                const int dxy = wide_val<PS>(pl + 2 * PS, px * LS + py, ds);
+                const int dxy = wide_val<PS>(pl + 2 * PS, __umul24(px, LS) + py, ds);
                 const int base = 2 * acc[i] - rx.da - cy.da;
                 int del;
                 if constexpr (ZD)
