@@ -245,13 +245,24 @@ __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF,
 // Clamp to [-vmax, vmax] (S_v); values are finite, so med3 is the clamp.
 __device__ __forceinline__ float clampv(float t, float vmax) { return __builtin_amdgcn_fmed3f(t, -vmax, vmax); }
 
-// Rows of X, P^L and P^G in one column and the coefficients of their
-// attraction terms (velocity equation): row xr gets s2 ax + s3 bx, row lr
-// (!= xr) s2 + s3 bl, row gr (!= xr, lr) s3; every other row none.
+// Rows of X, P^L and P^G in one column and their attraction terms (velocity
+// equation) in binary64: row xr gets ox = s2 ax + s3 bx (ax, bx in {-1, 0}),
+// row lr (!= xr) ol = s2 + s3 bl (bl in {0, 1}), row gr (!= xr, lr) s3; every
+// other row none.  s2 = c2 r2 and s3 = c3 r3 are exact in binary64.
 struct Attract {
     int xr, lr, gr;
-    float ax, bx, bl;
+    double ox, ol;
 };
+
+// An attraction cell: c1 x + o evaluated in binary64 (c1 x is exact there) and
+// rounded once to binary32, then clamped (S_v).  In binary32 the two
+// roundings before c1 x and the terms cancel could leave an error that is
+// large next to the result, and late in a run a column's mass can sit on
+// such a cell.
+__device__ __forceinline__ float attract_cell(float c1, float x, double o, float vmax)
+{
+    return clampv((float)__fma_rn((double)c1, (double)x, o), vmax);
+}
 
 // Buffer resource over one particle's n x n matrix (raw, 32-bit elements):
 // row offsets go to the scalar offset, the lane's column to the vector one.
@@ -273,34 +284,32 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 // The attraction cells among rows [lo, hi) of column c: ex, el, eg are the
 // raw V(t) values at rows xr, lr, gr (read only where the row is in range).
 // Each is stored after the plain value of the same cell by the same lane
-// (program order), while its line is still in L2, and replaces that value in
-// the sum.
+// (program order) and replaces that value in the binary64 column sum.
 __device__ __forceinline__ void fix_cells(__amdgpu_buffer_rsrc_t rq, uint32_t col, uint32_t rowb, int lo, int hi,
                                           const Attract& at, float ex, float el, float eg, float sc, float c1,
-                                          float s2, float s3, float vmax, float& sum, float& vx)
+                                          double s3, float vmax, double& sum, float& vx)
 {
     if (at.xr >= lo && at.xr < hi) {
         const float x = __fmul_rn(ex, sc);
         vx = x;
-        // rows of X, P^L and P^G all equal: both terms vanish and the plain
-        // value stands (a re-store would cost a partial write of its line)
-        if (at.ax != 0.0f || at.bx != 0.0f) {
-            const float t =
-                clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), __fmul_rn(s2, at.ax)), __fmul_rn(s3, at.bx)), vmax);
-            sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        // no attraction term (rows of X, P^L and P^G equal): the plain value
+        // stands (a re-store would cost a partial write of its line)
+        if (at.ox != 0.0) {
+            const float t = attract_cell(c1, x, at.ox, vmax);
+            sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
             bstore(rq, col + __umul24(at.xr, rowb), 0u, t);
         }
     }
     if (at.lr != at.xr && at.lr >= lo && at.lr < hi) {
         const float x = __fmul_rn(el, sc);
-        const float t = clampv(__fadd_rn(__fadd_rn(__fmul_rn(c1, x), s2), __fmul_rn(s3, at.bl)), vmax);
-        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        const float t = attract_cell(c1, x, at.ol, vmax);
+        sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
         bstore(rq, col + __umul24(at.lr, rowb), 0u, t);
     }
     if (at.gr != at.xr && at.gr != at.lr && at.gr >= lo && at.gr < hi) {
         const float x = __fmul_rn(eg, sc);
-        const float t = clampv(__fadd_rn(__fmul_rn(c1, x), s3), vmax);
-        sum = __fadd_rn(sum, fabsf(t) - fabsf(clampv(__fmul_rn(c1, x), vmax)));
+        const float t = attract_cell(c1, x, s3, vmax);
+        sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
         bstore(rq, col + __umul24(at.gr, rowb), 0u, t);
     }
 }
@@ -318,17 +327,19 @@ __device__ __forceinline__ void top2(float x, int u, float& m1, int& u1, float& 
 }
 
 // Column c of the velocity pass over one particle's V(t) (rp) into V(t+1)
-// before the column norm (rq): returns the sum of |.| and the column's
+// before the column norm (rq): returns the sum of |.| (accumulated in
+// binary64: the attraction cells replace their plain values in it, which in
+// binary32 would leave the rounding of the larger running sum) and the column's
 // largest V(t) value m1 (first row r1), its runner-up m2, and vx = V(t) at
 // the X row.  Rows are loaded in batches so that many loads are in flight;
 // the attraction cells of a batch are read with it and fixed right after it.
-__device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
-                                               float sc, float c1, float s2, float s3, float vmax, const Attract& at,
-                                               float& m1, int& r1, float& m2, float& vx)
+__device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
+                                                float sc, float c1, double s3, float vmax, const Attract& at,
+                                                float& m1, int& r1, float& m2, float& vx)
 {
     constexpr int B = 32;
     const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)n;
-    float sum = 0.0f;
+    double sum = 0.0;
     int r0 = 0;
     for (; r0 + B <= n; r0 += B) {
         float v[B];
@@ -346,11 +357,11 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
             const float x = __fmul_rn(v[u], sc);
             top2(x, u, m1, u1, m2);
             const float t = clampv(__fmul_rn(c1, x), vmax);
-            sum = __fadd_rn(sum, fabsf(t));
+            sum += (double)fabsf(t);
             bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
         }
         r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
-        fix_cells(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s2, s3, vmax, sum, vx);
+        fix_cells(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
     const int lo = r0;
     for (int r = r0; r < n; ++r) {
@@ -360,14 +371,14 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
         top2(x, 0, m1, u1, m2);
         r1 = m1 != mb ? r : r1;
         const float t = clampv(__fmul_rn(c1, x), vmax);
-        sum = __fadd_rn(sum, fabsf(t));
+        sum += (double)fabsf(t);
         bstore(rq, col, (uint32_t)r * rowb, t);
     }
     if (lo < n) {
         const float ex = bload(rp, col + __umul24(at.xr >= lo ? at.xr : lo, rowb), 0u);
         const float el = bload(rp, col + __umul24(at.lr >= lo ? at.lr : lo, rowb), 0u);
         const float eg = bload(rp, col + __umul24(at.gr >= lo ? at.gr : lo, rowb), 0u);
-        fix_cells(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s2, s3, vmax, sum, vx);
+        fix_cells(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
     return sum;
 }
@@ -392,8 +403,8 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
     float* Vq = d.V[cur ^ 1] + (size_t)k * n * n;
     const uint8_t* Xk = d.X[cur] + (size_t)k * n;
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-    const float s2 = __fmul_rn(d.c2, unit_float(rb.w[0]));
-    const float s3 = __fmul_rn(d.c3, unit_float(rb.w[1]));
+    const double s2 = (double)d.c2 * (double)unit_float(rb.w[0]);  // exact
+    const double s3 = (double)d.c3 * (double)unit_float(rb.w[1]);
     const float c1 = d.c1, vmax = d.vmax;
 
     // ---- A. velocity stream + SecondTarget caches
@@ -410,19 +421,19 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
         const int c = l + kWave * kk;
         const bool on = c < n;
         int xr = 0;
-        float m1 = -INFINITY, m2 = -INFINITY, sum = 0.0f, vx = 0.0f;
+        float m1 = -INFINITY, m2 = -INFINITY, vx = 0.0f;
+        double sum = 0.0;
         int r1 = -1;
         if (on) {
             Attract at;
             xr = at.xr = Xk[c];
             at.lr = d.PL[(size_t)k * n + c];
             at.gr = d.PG[(size_t)gl * n + c];
-            at.ax = (float)((at.xr == at.lr) - 1);
-            at.bx = (float)((at.xr == at.gr) - 1);
-            at.bl = (float)(at.lr == at.gr);
+            at.ox = s2 * (double)((at.xr == at.lr) - 1) + s3 * (double)((at.xr == at.gr) - 1);
+            at.ol = s2 + s3 * (double)(at.lr == at.gr);
             const float sc = Sp[c];
-            sum = stream_column(rp, rq, c, n, sc, c1, s2, s3, vmax, at, m1, r1, m2, vx);
-            Sq[c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
+            sum = stream_column(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
+            Sq[c] = (d.norm && sum > 0.0) ? (float)(1.0 / sum) : 1.0f;
         }
         // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
         // when the column maximum is unique and off the Z row; the runner-up

@@ -64,25 +64,28 @@ __global__ void k_velocity(InstDesc d)
     const int gl = k / d.S;  // swarm within this descriptor; g: within the instance
     const uint32_t g = (uint32_t)(gl + d.swarm_base), s = (uint32_t)(k % d.S);
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-    const float s2 = __fmul_rn(d.c2, unit_float(rb.w[0]));
-    const float s3 = __fmul_rn(d.c3, unit_float(rb.w[1]));
+    // c2 r2, c3 r3 and c1 x are exact in binary64: an attraction cell is
+    // c1 x + s2 a + s3 b evaluated there and rounded once (the terms can
+    // cancel); the column sum is accumulated in binary64 as well
+    const double s2 = (double)d.c2 * (double)unit_float(rb.w[0]);
+    const double s3 = (double)d.c3 * (double)unit_float(rb.w[1]);
     const int x = d.X[cur][(size_t)k * n + c];
     const int pl = d.PL[(size_t)k * n + c];
     const int pg = d.PG[(size_t)gl * n + c];
     const float* Vc = d.V[cur] + (size_t)k * n * n;
     const float sc = d.Vinv[cur][(size_t)k * n + c];
     float* Vn = d.V[cur ^ 1] + (size_t)k * n * n;
-    float sum = 0.0f;
+    double sum = 0.0;
     for (int r = 0; r < n; ++r) {
-        const float a = (float)((r == pl) - (r == x)), b = (float)((r == pg) - (r == x));
-        float t = __fmul_rn(d.c1, __fmul_rn(Vc[(size_t)r * n + c], sc));
-        t = __fadd_rn(t, __fmul_rn(s2, a));
-        t = __fadd_rn(t, __fmul_rn(s3, b));
+        const int a = (r == pl) - (r == x), b = (r == pg) - (r == x);
+        const float v = __fmul_rn(Vc[(size_t)r * n + c], sc);
+        float t = (a | b) ? (float)__fma_rn((double)d.c1, (double)v, s2 * (double)a + s3 * (double)b)
+                          : __fmul_rn(d.c1, v);
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
-        sum = __fadd_rn(sum, fabsf(t));
+        sum += (double)fabsf(t);
         Vn[(size_t)r * n + c] = t;
     }
-    d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
+    d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && sum > 0.0) ? (float)(1.0 / sum) : 1.0f;
 }
 
 // ------------------------------------------------------------------ S_x

@@ -70,13 +70,13 @@ WORKLOADS = {
     # n = 50 dense symmetric U{0..99}; 10 x 1000, 1000 iterations, int32 path
     "n50": dict(gen=lambda: uniform_instance(50, 0, 99, 102), num_swarms=10, particles_per_swarm=1000,
                 iterations=1000, migration=False),
-    # n = 100 Euclidean D, sparse heavy-tailed F; 20 x 500, migration every 50 iterations
+    # n = 100 Euclidean D, sparse heavy-tailed F (both outside int8); 20 x 500, migration every 50 iterations
     "n100mig": dict(gen=lambda: euclid_sparse_instance(100, 103), num_swarms=20, particles_per_swarm=500,
                     iterations=2000, migration=True, migration_factor=0.33, migration_period=50),
     # n = 128 symmetric U{0..127} (int8-representable); 8 x 512
     "n128": dict(gen=lambda: uniform_instance(128, 0, 127, 104), num_swarms=8, particles_per_swarm=512,
                  iterations=200, migration=False),
-    # same with D in U{0..1000}: outside int8, exercises the int32 path
+    # same with D in U{0..1000}: outside int8 (byte-split MFMA on the fused engine, int32 on the per-stage one)
     "n128wide": dict(gen=lambda: uniform_instance(128, 0, 127, 1041, d_hi=1000), num_swarms=8,
                      particles_per_swarm=512, iterations=200, migration=False),
     # headline: n = 128 instance above with 200 swarms x 50 particles = 10,000 particles
