@@ -110,24 +110,28 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             if constexpr (!SYM) dpt[b][kc] = y < n ? gather16<LS>(sD, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
         }
     }
-    // diagonal tiles: A_xx (and B_xx) -> row info, goal = trace(A); int8 entries and
-    // n <= 160 bound |goal| by 160^2 * 127^2 < 2^31
+    // diagonal terms: A_xx = sum_k F[x][k] Dp[x][k] (and B_xx) as a dot product of
+    // the lane's own fragments (4 int8 products per instruction), the two half-waves'
+    // K halves added across; row info, goal = trace(A); int8 entries and n <= 160
+    // bound |goal| by 160^2 * 127^2 < 2^31
     int gsum = 0;
 #pragma unroll
     for (int a = 0; a < T; ++a) {
-        v16i acc = {};
-        v16i accb = {};
+        int da = 0, db = 0;
 #pragma unroll
         for (int kc = 0; kc < T; ++kc) {
-            acc = mfma32(frag16<LS>(sF, 32 * a + lc, 32 * kc + 16 * h), dp[a][kc], acc);
-            if constexpr (!SYM) accb = mfma32(frag16<LS>(sFT, 32 * a + lc, 32 * kc + 16 * h), dpt[a][kc], accb);
-        }
-        if (h == ((lc >> 2) & 1)) {
-            const int want = 4 * (lc >> 3) + (lc & 3);
-            int da = 0, db = 0;
+            const v4i f = frag16<LS>(sF, 32 * a + lc, 32 * kc + 16 * h);
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i == want) { da = acc[i]; if constexpr (!SYM) db = accb[i]; }
+            for (int w = 0; w < 4; ++w) da = __builtin_amdgcn_sdot4(f[w], dp[a][kc][w], da, false);
+            if constexpr (!SYM) {
+                const v4i g = frag16<LS>(sFT, 32 * a + lc, 32 * kc + 16 * h);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) db = __builtin_amdgcn_sdot4(g[w], dpt[a][kc][w], db, false);
+            }
+        }
+        da += __shfl_xor(da, 32, kWave);
+        if constexpr (!SYM) db += __shfl_xor(db, 32, kWave);
+        if (h == 0) {
             const int x = 32 * a + lc;
             if (x < n) {
                 gsum += da;
