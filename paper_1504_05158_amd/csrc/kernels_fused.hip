@@ -44,6 +44,11 @@ __device__ __forceinline__ void wave_sync()
 template <int NP>
 constexpr int lds_stride() { return NP + 16; }
 
+// D and D^T are only gathered byte-wise (and read at single cells), which
+// padding does not help: they keep the unpadded stride.
+template <int NP>
+constexpr int lds_stride_d() { return NP; }
+
 // 16 bytes Mt[p[kb + j]][py], j = 0..15, packed little-endian into 4 ints:
 // with Mt the transpose of M this is M[py][p[kb + j]].  For a fixed j every
 // lane of a half-wave reads the same row (kb does not depend on the lane) at
@@ -80,10 +85,10 @@ __device__ __forceinline__ v16i mfma32(v4i a, v4i b, v16i c)
 // acc element i of lane l in a 32x32 tile: row 8(i/4) + 4(l/32) + i%4, column l%32
 __device__ __forceinline__ int tile_row(int i, int h) { return 8 * (i >> 2) + 4 * h + (i & 3); }
 
-// Row info per index x: p_x, f_xx, Dp_xx, diagonal term dA_x (A_xx when F and
-// D are symmetric, else A_xx + B_xx).
+// Row info per index x: p_x and the diagonal term dA_x (A_xx when F and D are
+// symmetric, else A_xx + B_xx); f_xx and Dp_xx are read from the matrices.
 struct RowInfo {
-    int p, f, dp, da;
+    int p, da;
 };
 
 // Stage C for one permutation held in LDS (sp, NP bytes, entries >= n are 0).
@@ -94,7 +99,7 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                                 const uint8_t* sp, RowInfo* sri, bool want_pairs, long long* dout, long long& goal,
                                 long long& bestkey)
 {
-    constexpr int T = NP / 32, LS = lds_stride<NP>();
+    constexpr int T = NP / 32, LS = lds_stride<NP>(), LSD = lds_stride_d<NP>();
     const int l = lane_id(), h = l >> 5, lc = l & 31;
     // Dp (and Dp' for the general case) fragments for every (block, K chunk):
     // Dp[y][k] = D[p_y][p_k] = D^T[p_k][p_y], Dp'[y][k] = D^T[p_y][p_k] = D[p_k][p_y]
@@ -106,8 +111,8 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
         const int py = y < n ? (int)sp[y] : 0;
 #pragma unroll
         for (int kc = 0; kc < T; ++kc) {
-            dp[b][kc] = y < n ? gather16<LS>(SYM ? sD : sDT, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
-            if constexpr (!SYM) dpt[b][kc] = y < n ? gather16<LS>(sD, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            dp[b][kc] = y < n ? gather16<LSD>(SYM ? sD : sDT, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
+            if constexpr (!SYM) dpt[b][kc] = y < n ? gather16<LSD>(sD, py, sp, 32 * kc + 16 * h) : v4i{0, 0, 0, 0};
         }
     }
     // diagonal terms: A_xx = sum_k F[x][k] Dp[x][k] (and B_xx) as a dot product of
@@ -138,8 +143,6 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                 const int px = sp[x];
                 RowInfo ri;
                 ri.p = px;
-                ri.f = sF[x * LS + x];
-                ri.dp = sD[px * LS + px];
                 ri.da = SYM ? da : da + db;
                 sri[x] = ri;
             }
@@ -176,30 +179,36 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             __builtin_amdgcn_sched_barrier(0);
             if (y >= n) continue;
             const RowInfo cy = sri[y];
+            const int cyf = (SYM && ZD) ? 0 : sF[y * (LS + 1)];             // f_yy
+            const int cyd = (SYM && ZD) ? 0 : sD[__umul24(cy.p, LSD + 1)];  // Dp_yy
             // lane rows x = 32a + 4h + xo(i), xo(i) = 8(i/4) + i%4, increasing in i:
             // the first strict minimum over i is the lexicographic (delta, x) minimum
             const RowInfo* rxb = sri + 32 * a + 4 * h;
             const int8_t* fxb = sF + (32 * a + 4 * h) * LS + y;
             const int8_t* fyb = sF + y * LS + 32 * a + 4 * h;
             // ZD: the minimum is taken over hdel = (A_xy + A_yx - A_xx) + 2 f_xy Dp_xy,
-            // delta = 2 (hdel - A_yy): increasing in hdel, so the same first minimum
-            int tmin = INT_MAX, ti = 0;
+            // delta = 2 (hdel - A_yy): increasing in hdel, so the same first minimum.
+            // The minimum is kept as one int, delta * 16 + i (|delta| < 2^26 for int8
+            // entries and n <= 160): the smallest delta, then the first element.
+            int tkey = INT_MAX;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int xo = 8 * (i >> 2) + (i & 3);
                 if (a == b && 32 * a + 4 * h + xo >= y) continue;  // diagonal tiles: x < y only
                 const RowInfo rx = rxb[xo];
                 const int fxy = fxb[xo * LS];
-                const int dxy = sD[__umul24(rx.p, LS) + cy.p];  // 24-bit multiply: p < 256
+                const int dxy = sD[__umul24(rx.p, LSD) + cy.p];  // 24-bit multiply: p < 256
                 int del;
                 if constexpr (SYM && ZD) {
                     del = A[i] - rx.da + 2 * fxy * dxy;
                 } else if constexpr (SYM) {
-                    del = 2 * (A[i] - rx.da - cy.da) + (2 * fxy - rx.f - cy.f) * (2 * dxy - rx.dp - cy.dp);
+                    const int rxf = sF[(32 * a + 4 * h + xo) * (LS + 1)], rxd = sD[__umul24(rx.p, LSD + 1)];
+                    del = 2 * (A[i] - rx.da - cy.da) + (2 * fxy - rxf - cyf) * (2 * dxy - rxd - cyd);
                 } else {
                     const int fyx = fyb[xo];
-                    const int dyx = sD[__umul24(cy.p, LS) + rx.p];
-                    const int faa = rx.f, fbb = cy.f, daa = rx.dp, dbb = cy.dp;
+                    const int dyx = sD[__umul24(cy.p, LSD) + rx.p];
+                    const int faa = sF[(32 * a + 4 * h + xo) * (LS + 1)], fbb = cyf;
+                    const int daa = sD[__umul24(rx.p, LSD + 1)], dbb = cyd;
                     const int kap = (faa - fyx) * (dyx - daa) + (fxy - fbb) * (dbb - dxy) + (faa - fxy) * (dxy - daa) +
                                     (fyx - fbb) * (dbb - dyx);
                     const int lam = (faa - fbb) * (dbb - daa) + (fxy - fyx) * (dyx - dxy);
@@ -211,12 +220,12 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
                     dout[(size_t)x * n + y] = full;
                     dout[(size_t)y * n + x] = full;
                 }
-                const bool lt = del < tmin;
-                tmin = lt ? del : tmin;
-                ti = lt ? i : ti;
+                tkey = min(tkey, (int)((uint32_t)del << 4) | i);
                 __builtin_amdgcn_sched_barrier(0);
             }
-            if (tmin != INT_MAX) {
+            if (tkey != INT_MAX) {
+                int tmin = tkey >> 4;
+                const int ti = tkey & 15;
                 if constexpr (SYM && ZD) tmin = 2 * (tmin - cy.da);
                 // (delta, x, y) as one ordered 64-bit key: delta * 2^16 + x * 2^8 + y
                 const int x = 32 * a + 4 * h + 8 * (ti >> 2) + (ti & 3);
@@ -232,16 +241,16 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
 template <int NP, bool SYM>
 __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF, int8_t* sD, int8_t* sFT, int8_t* sDT)
 {
-    constexpr int LS = lds_stride<NP>(), RV = NP / 16;  // 16-byte chunks per row
+    constexpr int LS = lds_stride<NP>(), LSD = lds_stride_d<NP>(), RV = NP / 16;  // 16-byte chunks per row
     const v4i* F = reinterpret_cast<const v4i*>(d.F8);
     const v4i* D = reinterpret_cast<const v4i*>(d.D8);
     for (int i = threadIdx.x; i < NP * RV; i += blockDim.x) {
-        const int o = (i / RV) * LS + 16 * (i % RV);
+        const int o = (i / RV) * LS + 16 * (i % RV), od = (i / RV) * LSD + 16 * (i % RV);
         *reinterpret_cast<v4i*>(sF + o) = F[i];
-        *reinterpret_cast<v4i*>(sD + o) = D[i];
+        *reinterpret_cast<v4i*>(sD + od) = D[i];
         if constexpr (!SYM) {
             *reinterpret_cast<v4i*>(sFT + o) = reinterpret_cast<const v4i*>(d.FT8)[i];
-            *reinterpret_cast<v4i*>(sDT + o) = reinterpret_cast<const v4i*>(d.DT8)[i];
+            *reinterpret_cast<v4i*>(sDT + od) = reinterpret_cast<const v4i*>(d.DT8)[i];
         }
     }
 }
@@ -531,12 +540,16 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
     const InstDesc& d = TABLE ? descs[bm.x] : one;
     constexpr int CPL = cols_per_lane<NP>();  // column slots per lane
     __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride_d<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride_d<NP>()];
     __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
-    __shared__ RowInfo sri[kWaves][NP];
-    __shared__ StLds<CPL> slds[kWaves];
+    // per wave: the selection scratch of stage B, then the row info of stage C
+    union WaveScratch {
+        StLds<CPL> st;
+        RowInfo ri[NP];
+    };
+    __shared__ WaveScratch sws[kWaves];
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
     __syncthreads();
 
@@ -545,11 +558,11 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
     const int k = bm.y + w;
     if (k >= d.P) return;
     uint8_t* pw = sp[w];
-    const int cur = velocity_and_target<NP, CPL>(d, k, pw, &slds[w]);
+    const int cur = velocity_and_target<NP, CPL>(d, k, pw, &sws[w].st);
     long long goal;
     int ba, bb;
     exchanges(d, pw, [&](long long& g, long long& key) {
-        goal_delta_mfma<NP, SYM, ZD>(d.n, sF, sD, sFT, sDT, pw, sri[w], d.ls != 0, nullptr, g, key);
+        goal_delta_mfma<NP, SYM, ZD>(d.n, sF, sD, sFT, sDT, pw, sws[w].ri, d.ls != 0, nullptr, g, key);
     }, goal, ba, bb);
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
@@ -802,9 +815,9 @@ __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __
                                                    long long* __restrict__ goals, long long* __restrict__ deltas)
 {
     __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride_d<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride_d<NP>()];
     __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
     __shared__ RowInfo sri[kWaves][NP];
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
