@@ -298,11 +298,13 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 // raw V(t) values at rows xr, lr, gr (read only where the row is in range).
 // Each is stored after the plain value of the same cell by the same lane
 // (program order) and replaces that value in the binary64 column sum.
+// X: whether the X-row cell is handled here too (else it was stored already).
+template <bool X>
 __device__ __forceinline__ void fix_cells(__amdgpu_buffer_rsrc_t rq, uint32_t col, uint32_t rowb, int lo, int hi,
                                           const Attract& at, float ex, float el, float eg, float sc, float c1,
                                           double s3, float vmax, double& sum, float& vx)
 {
-    if (at.xr >= lo && at.xr < hi) {
+    if (X && at.xr >= lo && at.xr < hi) {
         const float x = __fmul_rn(ex, sc);
         vx = x;
         // no attraction term (rows of X, P^L and P^G equal): the plain value
@@ -346,6 +348,9 @@ __device__ __forceinline__ void top2(float x, int u, float& m1, int& u1, float& 
 // largest V(t) value m1 (first row r1), its runner-up m2, and vx = V(t) at
 // the X row.  Rows are loaded in batches so that many loads are in flight;
 // the attraction cells of a batch are read with it and fixed right after it.
+// FOLDX: the X-row cell by a select (at npad >= 128, where it costs no
+// registers), else re-stored like the others.
+template <bool FOLDX>
 __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
                                                 float sc, float c1, double s3, float vmax, const Attract& at,
                                                 float& m1, int& r1, float& m2, float& vx)
@@ -363,18 +368,28 @@ __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amd
         const float ex = bload(rp, col + __umul24(at.xr >= r0 && at.xr < hi ? at.xr : r0, rowb), 0u);
         const float el = bload(rp, col + __umul24(at.lr >= r0 && at.lr < hi ? at.lr : r0, rowb), 0u);
         const float eg = bload(rp, col + __umul24(at.gr >= r0 && at.gr < hi ? at.gr : r0, rowb), 0u);
+        // the X-row cell (one in every column) takes its attraction value by a
+        // select before the row's single store; the P^L and P^G cells (which
+        // equal the X row or each other more and more often late in a run) are
+        // re-stored after the batch: a second store to a line just written
+        // leaves L2 as a partial write of its own, and three selects per row
+        // would cost the registers of a wave per SIMD
+        const float tx = attract_cell(c1, __fmul_rn(ex, sc), at.ox, vmax);
+        const int dx = FOLDX ? at.xr - r0 : -1;
+        if (FOLDX && dx >= 0 && dx < B) vx = __fmul_rn(ex, sc);
         const float mb = m1;
         int u1 = 0;
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const float x = __fmul_rn(v[u], sc);
             top2(x, u, m1, u1, m2);
-            const float t = clampv(__fmul_rn(c1, x), vmax);
+            float t = clampv(__fmul_rn(c1, x), vmax);
+            if constexpr (FOLDX) t = u == dx ? tx : t;
             sum += (double)fabsf(t);
             bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
         }
         r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
-        fix_cells(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
+        fix_cells<!FOLDX>(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
     const int lo = r0;
     for (int r = r0; r < n; ++r) {
@@ -391,7 +406,7 @@ __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amd
         const float ex = bload(rp, col + __umul24(at.xr >= lo ? at.xr : lo, rowb), 0u);
         const float el = bload(rp, col + __umul24(at.lr >= lo ? at.lr : lo, rowb), 0u);
         const float eg = bload(rp, col + __umul24(at.gr >= lo ? at.gr : lo, rowb), 0u);
-        fix_cells(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
+        fix_cells<true>(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
     return sum;
 }
@@ -445,7 +460,7 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
             at.ox = s2 * (double)((at.xr == at.lr) - 1) + s3 * (double)((at.xr == at.gr) - 1);
             at.ol = s2 + s3 * (double)(at.lr == at.gr);
             const float sc = Sp[c];
-            sum = stream_column(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
+            sum = stream_column<NP >= 128>(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
             Sq[c] = (d.norm && sum > 0.0) ? (float)(1.0 / sum) : 1.0f;
         }
         // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
