@@ -86,3 +86,35 @@ def test_range_errors_on_host(L):
     D = np.full((8, 8), 1 << 14, np.int32)
     rc, h = _init(L, F, D, delta_path="int32")
     assert rc == -2 and not h.value
+
+
+def test_header_enums_match_the_binding():
+    import paper_1504_05158_amd as q
+    src = open(HEADER).read()
+    vals = dict((k, int(v)) for k, v in re.findall(r"\b(QAP_(?:PATH|SX|ENGINE|SV|ERR)_\w+)\s*=\s*(-?\d+)", src))
+    for name in ("QAP_PATH_AUTO", "QAP_PATH_INT8_MFMA", "QAP_PATH_INT32", "QAP_PATH_SPLIT_MFMA", "QAP_ERR_RANGE"):
+        assert name in vals, name
+    for name, v in vals.items():
+        if hasattr(q, name):
+            assert getattr(q, name) == v, name
+
+
+def test_split_path_range_errors_on_host(L):
+    import paper_1504_05158_amd as q
+    # asymmetric data outside int8: no byte-split path
+    F = np.arange(64, dtype=np.int32).reshape(8, 8) * 5
+    D = np.full((8, 8), 3, np.int32)
+    rc, h = _init(L, F, D, delta_path="split")
+    assert rc == q.QAP_ERR_RANGE and not h.value
+    # symmetric, but an entry beyond 15 bits
+    F = np.full((8, 8), 16384, np.int32)
+    rc, h = _init(L, F, D, delta_path="split")
+    assert rc == q.QAP_ERR_RANGE and not h.value
+    # symmetric and 15-bit, but 8 (n + 3) max|F| max|D| >= 2^31
+    F = np.full((8, 8), 16383, np.int32)
+    D = np.full((8, 8), 1500, np.int32)
+    rc, h = _init(L, F, D, delta_path="split")
+    assert rc == q.QAP_ERR_RANGE and not h.value
+    # an unknown path value
+    rc, h = _init(L, F, F, delta_path=4)
+    assert rc == q.QAP_ERR_INVALID_ARG and not h.value
