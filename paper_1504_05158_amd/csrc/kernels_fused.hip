@@ -268,10 +268,9 @@ struct Attract {
 };
 
 // An attraction cell: c1 x + o evaluated in binary64 (c1 x is exact there) and
-// rounded once to binary32, then clamped (S_v).  In binary32 the two
-// roundings before c1 x and the terms cancel could leave an error that is
-// large next to the result, and late in a run a column's mass can sit on
-// such a cell.
+// rounded once to binary32, then clamped (S_v): in binary32 the roundings of
+// c1 x and of c2 r2, c3 r3 before the terms cancel could leave an error that
+// is large next to the result.
 __device__ __forceinline__ float attract_cell(float c1, float x, double o, float vmax)
 {
     return clampv((float)__fma_rn((double)c1, (double)x, o), vmax);
