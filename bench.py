@@ -91,18 +91,27 @@ def contraction_ops(n: int, sym: bool) -> int:
     return 2 * n ** 3 * (1 if sym else 2)
 
 
+def workload_setup(name: str):
+    """Instance, swarm layout and run parameters of a named workload: the
+    headline one (n128x10k) or another of qap_inputs.WORKLOADS."""
+    import qap_inputs as gen
+    w = gen.WORKLOADS[name]
+    F, D = w["gen"]()
+    run = dict(RUN, migration=w["migration"], migration_factor=w.get("migration_factor", 0.0),
+               migration_period=w.get("migration_period", 1))
+    return F, D, w["num_swarms"], w["particles_per_swarm"], run
+
+
 def run_gpu(args, engine: str):
     import numpy as np
     import torch
     import paper_1504_05158_amd as q
-    import qap_inputs as gen
 
-    n = WORKLOAD["n"]
-    F, D = gen.uniform_instance(n, 0, 127, WORKLOAD["seed_inst"])
+    F, D, m, S, run = workload_setup(args.workload)
+    n = F.shape[0]
     stream = torch.cuda.Stream()
-    kw = dict(stream=stream, engine=engine, num_swarms=WORKLOAD["num_swarms"],
-              particles_per_swarm=WORKLOAD["particles_per_swarm"], **RUN)
-    P = WORKLOAD["num_swarms"] * WORKLOAD["particles_per_swarm"]
+    kw = dict(stream=stream, engine=engine, num_swarms=m, particles_per_swarm=S, **run)
+    P = m * S
     sw = q.Swarm.create(F, D, **kw)
     path, sym = sw.path()
     groups = sw.stream_groups()
@@ -148,7 +157,8 @@ def run_gpu(args, engine: str):
             achieved = bps / (region_ms * 1e-3) / 1e9
         else:
             achieved = bps / (avg_ms * 1e-3) / 1e9
-        traffic = measured_traffic() if (dom == "fused" and engine == "fused") else None
+        headline = args.workload == WORKLOAD["name"]
+        traffic = measured_traffic() if (dom == "fused" and engine == "fused" and headline) else None
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic / 1e9, 4))
@@ -159,7 +169,7 @@ def run_gpu(args, engine: str):
         roof["achieved_per_launch"] = round(bps / launches / (avg_ms * 1e-3) / 1e9, 1)
     roof["kernel"] = dom
     roof["avg_ms"] = round(avg_ms, 4)  # per launch
-    return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, roofline=roof,
+    return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, n=n, roofline=roof,
                 stage_ms={k: round(v / max(iters, 1) / groups, 4) for k, v in stage_ms.items()}, best=best,
                 groups=groups)
 
@@ -197,6 +207,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--engine", default="fused", choices=["fused", "plain"])
+    ap.add_argument("--workload", default=WORKLOAD["name"],
+                    help="n128x10k (the headline, default) or another workload of qap_inputs.WORKLOADS "
+                         "(n12, n50, n100mig, n128, n128wide); the CPU baseline runs with the headline only")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-calibration", action="store_true",
@@ -223,8 +236,10 @@ def main():
             other = run_gpu(args, oth)
         except Exception as e:  # the other engine may be unavailable for this build
             other = dict(error=str(e))
+    headline = args.workload == WORKLOAD["name"]
     line = {
-        "metric": "particle-iterations/sec at n=128, 10k particles (batched int8 vs plain path)",
+        "metric": ("particle-iterations/sec at n=128, 10k particles (batched int8 vs plain path)" if headline
+                   else "particle-iterations/sec, workload %s" % args.workload),
         "value": round(res["value"], 1),
         "unit": "particle-iterations/s",
         "n_gpus": 1,
@@ -234,11 +249,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+i8" if res["path"] == "int8" else "f32+i32",
+        "dtype": {"int8": "f32+i8", "split": "f32+i8 byte-split"}.get(res["path"], "f32+i32"),
         "data": "synthetic",
-        "config": {"workload": "n128x10k: n=128 QAP, F and D symmetric U{0..127}, 200 swarms x 50 particles, "
-                               "Norm, c=(0.8,0.5,0.5), depth 2, one pair exchange",
-                   "n": WORKLOAD["n"], "particles": res["P"], "engine": args.engine, "delta_path": res["path"],
+        "config": {"workload": ("n128x10k: n=128 QAP, F and D symmetric U{0..127}, 200 swarms x 50 particles, "
+                                "Norm, c=(0.8,0.5,0.5), depth 2, one pair exchange") if headline else args.workload,
+                   "n": res["n"], "particles": res["P"], "engine": args.engine, "delta_path": res["path"],
                    "parallelism": "single GPU"},
         "roofline": res["roofline"],
         "stage_ms": res["stage_ms"],
@@ -247,7 +262,7 @@ def main():
     if other is not None:
         line["compare"] = {("plain" if args.engine == "fused" else "fused"):
                            (round(other["value"], 1) if "value" in other else other)}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and headline:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 

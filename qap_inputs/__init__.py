@@ -70,7 +70,7 @@ WORKLOADS = {
     # n = 50 dense symmetric U{0..99}; 10 x 1000, 1000 iterations, int32 path
     "n50": dict(gen=lambda: uniform_instance(50, 0, 99, 102), num_swarms=10, particles_per_swarm=1000,
                 iterations=1000, migration=False),
-    # n = 100 Euclidean D, sparse heavy-tailed F (both outside int8); 20 x 500, migration every 50 iterations
+    # n = 100 Euclidean D (at most 121 at this seed), sparse heavy-tailed F (outside int8); 20 x 500, migration every 50 iterations
     "n100mig": dict(gen=lambda: euclid_sparse_instance(100, 103), num_swarms=20, particles_per_swarm=500,
                     iterations=2000, migration=True, migration_factor=0.33, migration_period=50),
     # n = 128 symmetric U{0..127} (int8-representable); 8 x 512

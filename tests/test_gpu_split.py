@@ -71,7 +71,7 @@ CASES = [
     ("F-n37-neg", lambda: sym(37, (-3000, 3000), (0, 127), 2), 1),
     ("FD-n64-diag", lambda: sym(64, (-2000, 2000), (-300, 300), 3, zero_diag=False), 3),
     ("D-n100-diag", lambda: sym(100, (-128, 127), (0, 16383), 4, zero_diag=False), 2),
-    ("FD-n100-euclid", lambda: gen.euclid_sparse_instance(100, 103), 3),
+    ("F-n100-euclid", lambda: gen.euclid_sparse_instance(100, 103), 1),  # D at most 121 at this seed
     ("FD-n128", lambda: sym(128, (0, 2980), (0, 141), 5), 3),
     ("D-n150", lambda: sym(150, (0, 127), (0, 1000), 6), 2),
     ("F-n150-diag", lambda: sym(150, (-16384, 16383), (-20, 20), 7, zero_diag=False), 1),
