@@ -91,15 +91,37 @@ def contraction_ops(n: int, sym: bool) -> int:
     return 2 * n ** 3 * (1 if sym else 2)
 
 
+MIXED = dict(name="mixed64", count=64, seed=105, num_swarms=4, particles_per_swarm=64)
+WORKLOAD_NAMES = ["n128x10k", "n12", "n50", "n100mig", "n128", "n128wide", "mixed64"]
+
+
 def workload_setup(name: str):
-    """Instance, swarm layout and run parameters of a named workload: the
-    headline one (n128x10k) or another of qap_inputs.WORKLOADS."""
+    """Instances and run parameters of a named workload: a list of
+    (F, D, params) -- the headline one (n128x10k), another of
+    qap_inputs.WORKLOADS, or the 64-instance mixed-size batch (mixed64: n
+    uniform in 20..150, F and D U{0..99} symmetric, 4 swarms x 64 particles
+    each, one seed per instance)."""
     import qap_inputs as gen
+    if name == MIXED["name"]:
+        out = []
+        for k, (F, D) in enumerate(gen.mixed_batch(MIXED["count"], MIXED["seed"])):
+            out.append((F, D, dict(RUN, num_swarms=MIXED["num_swarms"],
+                                   particles_per_swarm=MIXED["particles_per_swarm"], seed=1 + k)))
+        return out
     w = gen.WORKLOADS[name]
     F, D = w["gen"]()
     run = dict(RUN, migration=w["migration"], migration_factor=w.get("migration_factor", 0.0),
-               migration_period=w.get("migration_period", 1))
-    return F, D, w["num_swarms"], w["particles_per_swarm"], run
+               migration_period=w.get("migration_period", 1), num_swarms=w["num_swarms"],
+               particles_per_swarm=w["particles_per_swarm"])
+    if name == "n50":
+        run["delta_path"] = "int32"  # that workload is defined on the plain int32 cost and delta path
+    return [(F, D, run)]
+
+
+def workload_bytes(insts, stage: str = "fused") -> int:
+    """Algorithmic HBM bytes of one step of the workload."""
+    return sum(algorithmic_bytes(stage, F.shape[0]) * p["num_swarms"] * p["particles_per_swarm"]
+               for F, D, p in insts)
 
 
 def run_gpu(args, engine: str):
@@ -107,13 +129,20 @@ def run_gpu(args, engine: str):
     import torch
     import paper_1504_05158_amd as q
 
-    F, D, m, S, run = workload_setup(args.workload)
+    insts = workload_setup(args.workload)
+    F, D = insts[0][0], insts[0][1]
     n = F.shape[0]
     stream = torch.cuda.Stream()
-    kw = dict(stream=stream, engine=engine, num_swarms=m, particles_per_swarm=S, **run)
-    P = m * S
-    sw = q.Swarm.create(F, D, **kw)
-    path, sym = sw.path()
+    P = sum(p["num_swarms"] * p["particles_per_swarm"] for _, _, p in insts)
+
+    def make():
+        prms = [q.make_params(stream=stream.cuda_stream, engine=engine, **p) for _, _, p in insts]
+        return q.Swarm([(A, B) for A, B, _ in insts], prms)
+
+    sw = make()
+    paths = sorted(set(sw.path(k)[0] for k in range(len(insts))))
+    path = paths[0] if len(paths) == 1 else "+".join(paths)
+    sym = all(sw.path(k)[1] for k in range(len(insts)))
     groups = sw.stream_groups()
     sw.step(args.warmup)
     sw.sync()
@@ -135,22 +164,25 @@ def run_gpu(args, engine: str):
     # per-kernel durations from HIP events on the streams the kernels run on: a
     # second run from the same seed replays exactly the timed iterations (events
     # stay out of the timed run, where they would add a few percent)
-    sw = q.Swarm.create(F, D, **kw)
-    sw.step(args.warmup)
-    sw.profile(True)
-    sw.step(args.steps)
-    stage_ms, iters = sw.profile(False)
-    best = sw.best()[0]
-    sw.close()
+    if args.no_profile_pass:
+        stage_ms, iters = {"fused": region_ms * args.steps * groups}, args.steps
+    else:
+        sw = make()
+        sw.step(args.warmup)
+        sw.profile(True)
+        sw.step(args.steps)
+        stage_ms, iters = sw.profile(False)
+        sw.close()
     dom = max(stage_ms, key=stage_ms.get)
     launches = groups if dom == "fused" else 1
     avg_ms = stage_ms[dom] / max(iters, 1) / launches
-    if dom == "goal_delta" and engine == "plain":
-        achieved = contraction_ops(n, sym) * P / (avg_ms * 1e-3) / 1e12
+    if dom == "goal_delta" and path == "int32":
+        achieved = sum(contraction_ops(A.shape[0], sym) * p["num_swarms"] * p["particles_per_swarm"]
+                       for A, _, p in insts) / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=VALU_INT_PEAK_TOPS, unit="TOP/s",
                     frac=round(achieved / VALU_INT_PEAK_TOPS, 4), traffic=None)
     else:
-        bps = algorithmic_bytes(dom, n) * P  # per step, over the `launches` concurrent launches
+        bps = workload_bytes(insts, dom)  # per step, over the `launches` concurrent launches
         if launches > 1:
             # concurrent launches overlap: the aggregate rate is the step's bytes over the
             # event-timed region per step (which also holds the small bests kernels)
@@ -170,22 +202,23 @@ def run_gpu(args, engine: str):
     roof["kernel"] = dom
     roof["avg_ms"] = round(avg_ms, 4)  # per launch
     return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, n=n, roofline=roof,
-                stage_ms={k: round(v / max(iters, 1) / groups, 4) for k, v in stage_ms.items()}, best=best,
-                groups=groups)
+                stage_ms={k: round(v / max(iters, 1) / groups, 4) for k, v in stage_ms.items()},
+                groups=groups, instances=len(insts))
 
 
-def cpu_baseline(target_s: float = 15.0, max_steps: int = 50):
-    """The oracle, as it stands, stepping the whole workload until about
-    target_s seconds have passed."""
+def cpu_baseline(target_s: float = 15.0, max_steps: int = 50, threads: int = 16, swarms: int | None = None):
+    """The oracle, as it stands, stepping the headline workload (or its first
+    `swarms` swarms: the same instance and per-particle work) until about
+    target_s seconds have passed, on `threads` OpenMP threads (at most the
+    host's cores)."""
     import oracle as orc
     import qap_inputs as gen
 
     n = WORKLOAD["n"]
     F, D = gen.uniform_instance(n, 0, 127, WORKLOAD["seed_inst"])
-    threads = max(1, min(16, os.cpu_count() or 1))
-    orc.set_threads(threads)
+    orc.set_threads(max(1, min(threads, os.cpu_count() or 1)))
     used = orc.get_threads()
-    S, per = WORKLOAD["num_swarms"], WORKLOAD["particles_per_swarm"]
+    S, per = swarms or WORKLOAD["num_swarms"], WORKLOAD["particles_per_swarm"]
     sw = orc.OracleSwarm(F, D, num_swarms=S, particles_per_swarm=per, **RUN)
     steps = 0
     t0 = time.perf_counter()
@@ -195,10 +228,40 @@ def cpu_baseline(target_s: float = 15.0, max_steps: int = 50):
         if time.perf_counter() - t0 >= target_s:
             break
     secs = time.perf_counter() - t0
+    what = "the whole workload" if swarms is None else "the first %d of its 200 swarms" % S
     return dict(value=round(S * per * steps / secs, 2), unit="particle-iterations/s", cores=used,
                 kind="oracle",
-                sample="the whole workload (%d swarms x %d particles, n=%d), iterations 1-%d, %d OpenMP threads, %.1f s"
-                       % (S, per, n, steps, used, secs))
+                sample="%s (%d swarms x %d particles, n=%d), iterations 1-%d, %d OpenMP thread%s, %.1f s"
+                       % (what, S, per, n, steps, used, "" if used == 1 else "s", secs))
+
+
+def trace_span(path: str, args) -> dict:
+    """Per-iteration span of the timed region in a rocprofv3 kernel trace
+    (csv) of `bench.py --no-compare --no-cpu-baseline --no-profile-pass`:
+    the dispatches that start after the last warm-up iteration has ended
+    (the k_finish dispatch number 1 + warmup x groups, by end time: one at
+    init, one per stream group per iteration), from the first start to the
+    last end, divided by the timed iterations."""
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    fin = sorted(e for name, b, e in rows if "k_finish" in name)
+    groups = args.groups
+    cut = fin[args.warmup * groups]  # end of the last warm-up iteration
+    timed = [(name, b, e) for name, b, e in rows if b > cut]
+    span_ns = max(e for _, _, e in timed) - min(b for _, b, _ in timed)
+    per_iter_ms = span_ns / 1e6 / args.steps
+    byts = workload_bytes(workload_setup(args.workload))
+    fused = [e - b for name, b, e in timed if "k_fused" in name]
+    return {"trace": os.path.basename(path), "workload": args.workload, "timed_iterations": args.steps,
+            "finish_dispatches_per_iteration": groups, "dispatches_in_timed_region": len(timed),
+            "k_finish_total": len(fin), "span_ms_per_iteration": round(per_iter_ms, 5),
+            "fused_dispatches": len(fused), "fused_mean_ms": round(sum(fused) / max(len(fused), 1) / 1e6, 5),
+            "algorithmic_gb_per_step": round(byts / 1e9, 4),
+            "achieved_gbs": round(byts / (per_iter_ms * 1e-3) / 1e9, 1),
+            "frac": round(byts / (per_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def main():
@@ -207,14 +270,22 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--engine", default="fused", choices=["fused", "plain"])
-    ap.add_argument("--workload", default=WORKLOAD["name"],
-                    help="n128x10k (the headline, default) or another workload of qap_inputs.WORKLOADS "
-                         "(n12, n50, n100mig, n128, n128wide); the CPU baseline runs with the headline only")
+    ap.add_argument("--workload", default=WORKLOAD["name"], choices=WORKLOAD_NAMES,
+                    help="n128x10k (the headline, default), a workload of qap_inputs.WORKLOADS, or mixed64 "
+                         "(64 instances, n 20..150); the CPU baseline runs with the headline only")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile-pass", action="store_true",
+                    help="skip the second, event-timed run (for kernel traces of the timed region alone)")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for scaling HBM byte counters)")
+    ap.add_argument("--trace-span", metavar="CSV",
+                    help="no GPU run: the per-iteration span of the timed region in a rocprofv3 kernel trace")
+    ap.add_argument("--groups", type=int, default=3, help="with --trace-span: stream groups of the traced run")
     args = ap.parse_args()
+    if args.trace_span:
+        print(json.dumps(trace_span(args.trace_span, args)))
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build runs the hot path on a single MI355X "
               "(the swarms would shard by swarm across GPUs, which is not built); use --gpus 1",
@@ -259,11 +330,15 @@ def main():
         "stage_ms": res["stage_ms"],
         "stream_groups": res["groups"],
     }
+    if res["instances"] > 1:
+        line["config"]["instances"] = res["instances"]
     if other is not None:
         line["compare"] = {("plain" if args.engine == "fused" else "fused"):
                            (round(other["value"], 1) if "value" in other else other)}
     if not args.no_cpu_baseline and headline:
         line["cpu_baseline"] = cpu_baseline()
+        # one core, on the first 8 swarms (400 particles: an iteration takes seconds)
+        line["cpu_baseline"]["one_core"] = cpu_baseline(target_s=10.0, threads=1, swarms=8)
     print(json.dumps(line), flush=True)
 
 

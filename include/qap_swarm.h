@@ -14,9 +14,9 @@
  * One iteration per particle:
  *   X(t+1) = S_x(X(t) + V(t))                 S_x = SecondTarget (Alg. 1)
  *   V(t+1) = S_v(c1 V + c2 r2 (P^L - X) + c3 r3 (P^G - X))   (eq. velocity)
- * then the goal of X(t+1), one best-improvement pair exchange (local
- * improvement; optional), the particle best P^L, the swarm best P^G, and in
- * migration mode Alg. 2 every `migration_period` iterations.
+ * then the goal of X(t+1), up to `local_search` best-improvement pair
+ * exchanges (local improvement; 0 = none), the particle best P^L, the swarm
+ * best P^G, and in migration mode Alg. 2 every `migration_period` iterations.
  *
  * Conventions shared by every entry point:
  *  - Return value: QAP_OK (0) or a negative QAP_ERR_* code.  No C++
@@ -138,8 +138,11 @@ typedef struct {
     int32_t iteration;
 } qap_state;
 
-/* Create a handle for one instance and run the initialisation (iteration 0:
- * random permutations, random velocities passed through S_v, goals, bests).
+/* Create a handle for one instance and run the initialisation, iteration 0
+ * (Sec. 3.3: particles start from random solutions; Table 2 counts a solution
+ * found at initialisation as iteration 0): random permutations by
+ * Fisher-Yates, random velocities vmax (2u - 1) passed through S_v (Sec. 3.1),
+ * their goals (eq. qap), P^L = X, the swarm bests P^G and the best-ever record.
  * Errors: QAP_ERR_INVALID_ARG (NULL, n outside [2,256], a parameter outside
  * the ranges above), QAP_ERR_RANGE (an MFMA path requested that the data do
  * not meet, or
@@ -148,13 +151,22 @@ typedef struct {
 int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out);
 
 /* Same for `count` independent instances that step together (each with its
- * own params and seed; the engine, delta_path and stream of prms[0] apply to
- * all).  Instance k is addressed by index k in the calls below. */
+ * own params and seed; the engine and stream of prms[0] apply to all).  Each
+ * instance is the method of Sec. 3.1-3.2 on its own data; the batching is the
+ * library's: one launch per kernel class serves every instance of the class
+ * (where the paper launches separate kernels per iteration, Sec. 3.3).
+ * Instance k is addressed by index k in the calls below.  Errors as for
+ * qap_swarm_init; prms[k].engine must equal prms[0].engine. */
 int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count,
                          qap_swarm** out);
 
 /* Enqueue `iterations` >= 0 iterations on the handle's stream and return
- * without waiting.  Device errors surface here or on a later call.
+ * without waiting.  One iteration of every particle: r2, r3 (Sec. 3.1),
+ * X(t+1) = S_x(X(t) + V(t)) (eq. position, Alg. 1 SecondTarget), V(t+1) by
+ * eq. velocity with S_v, the goal (eq. qap) and the local-improvement pair
+ * exchanges, P^L; then per swarm P^G and the best-ever record, and Alg. 2
+ * (migration, Sec. 3.2) every migration_period iterations.
+ * Device errors surface here or on a later call.
  * Independent swarms on the fused kernel are stepped as up to 3 groups of
  * swarms, each on a stream of the library's own: the groups start after the
  * work already on the handle's stream and the handle's stream continues after
@@ -167,36 +179,55 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
  * per iteration; a stream that cannot be captured keeps eager launches. */
 int qap_swarm_step(qap_swarm* h, int32_t iterations);
 
-/* *active (may be NULL) = 1 if qap_swarm_step replays captured graphs (0:
+/* Runtime introspection (no passage of the paper).
+ * *active (may be NULL) = 1 if qap_swarm_step replays captured graphs (0:
  * eager launches, before the first step, or while profiling); *streams (may be
  * NULL) = number of stream groups, i.e. concurrent launches of each stage per
  * iteration. */
 int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams);
 
-/* Wait for the handle's stream. */
+/* Wait for the handle's stream (runtime; no passage of the paper). */
 int qap_swarm_sync(qap_swarm* h);
 
-/* Best solution ever seen by an instance (waits first).  perm: n entries,
- * may be NULL; goal / iter_found may be NULL. */
+/* Best solution ever seen by an instance (waits first).  Kept apart from the
+ * swarm bests because Alg. 2 may replace a swarm's P^G by a worse solution
+ * (Sec. 3.2); the iteration it was found at is Table 2's "Iter".  perm: n
+ * entries, may be NULL; goal / iter_found may be NULL. */
 int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found);
 
-/* Current swarm-best goals (m entries) of an instance (waits first). */
+/* Current swarm-best goals (m entries, the goals of P^G of Sec. 3.2) of an
+ * instance (waits first). */
 int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals);
 
-/* Copy an instance's state to / from host buffers (waits first).  set_state
+/* Copy an instance's state -- each particle's X, V, P^L (Sec. 3.1) and each
+ * swarm's P^G (Sec. 3.2) -- to / from host buffers (waits first).  set_state
  * validates every permutation and returns QAP_ERR_INVALID_ARG on a bad one;
  * it requires V, X, PL, goal, goalPL, PG, goalPG and best_perm. */
 int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st);
 int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st);
 
 /* Evaluate `count` permutations (host, [count][n]) of an instance with the
- * handle's device contraction path: goals [count] and, if deltas is not NULL,
- * the full pair-exchange delta matrices [count][n][n] (delta(a,b) =
- * C(p with a, b exchanged) - C(p), zero diagonal).  Waits for the result. */
+ * handle's device contraction path: goals [count] (eq. qap) and, if deltas is
+ * not NULL, the full pair-exchange delta matrices [count][n][n] (delta(a,b) =
+ * C(p with a, b exchanged) - C(p), zero diagonal: the pair-exchange
+ * neighbourhood of Sec. 2.1).  Every permutation is validated
+ * (QAP_ERR_INVALID_ARG).  Waits for the result. */
 int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count,
                    int64_t* goals, int64_t* deltas);
 
-/* Path actually used by an instance: QAP_PATH_INT8_MFMA, QAP_PATH_SPLIT_MFMA
+/* The pair-exchange delta matrix (delta(a,b) = C(p with a, b exchanged) -
+ * C(p), Sec. 2.1, eq. qap) of the solution that particle `particle` of an
+ * instance took from S_x (eq. position, Alg. 1) in the last step, before its
+ * local-improvement exchanges: out [n][n] (caller-owned host memory, zero
+ * diagonal), and that permutation in perm [n] (may be NULL).  The selection is
+ * recomputed by the step's own S_x code from the buffers of the previous
+ * state, which the last step only read, and the deltas come from the
+ * instance's contraction path.  Errors: QAP_ERR_INVALID_ARG for a NULL out, a
+ * particle outside [0, m*S), or no step since init or set_state.  Waits. */
+int qap_swarm_deltas(qap_swarm* h, int32_t instance, int32_t particle, int64_t* out, int32_t* perm);
+
+/* Runtime introspection (no passage of the paper).
+ * Path actually used by an instance: QAP_PATH_INT8_MFMA, QAP_PATH_SPLIT_MFMA
  * or QAP_PATH_INT32 in *delta_path, and 1 in *symmetric if F and D are both
  * symmetric. */
 int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric);
@@ -215,7 +246,8 @@ enum { QAP_STATS_MAX_RANKS = 64, QAP_STATS_MAX_BINS = 4096 };
 int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
                     int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist);
 
-/* Kernel timing for measurement.  enable = 1 switches the handle to
+/* Kernel timing for measurement (runtime; no passage of the paper).
+ * enable = 1 switches the handle to
  * profiled stepping: every later qap_swarm_step launches its kernels one by
  * one (no graph) with HIP events recorded around each stage on the stream it
  * runs on, and the counters restart from zero; enable = 0 switches back.
@@ -232,6 +264,17 @@ int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* l
 
 /* Release every device and host resource of the handle (NULL is a no-op). */
 void qap_swarm_destroy(qap_swarm* h);
+
+/* Test hooks for the failure paths (no passage of the paper).
+ * qap_swarm_fail_alloc(k), k >= 1: the k-th device allocation the library
+ * makes from now on (in any call, process-wide) fails as if the device were
+ * out of memory, once; k = 0 cancels.  The call that meets it returns
+ * QAP_ERR_NOMEM having released what it had allocated (an init leaves no
+ * handle; any other call leaves the handle usable).
+ * qap_swarm_live_allocations: the number of device allocations the library
+ * currently holds. */
+int qap_swarm_fail_alloc(int32_t nth);
+int64_t qap_swarm_live_allocations(void);
 
 /* Static text for a return code. */
 const char* qap_swarm_strerror(int code);

@@ -30,8 +30,8 @@ QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
 
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
-           "qap_swarm_path", "qap_swarm_graph", "qap_swarm_stats", "qap_swarm_profile", "qap_swarm_destroy",
-           "qap_swarm_strerror"]
+           "qap_swarm_deltas", "qap_swarm_path", "qap_swarm_graph", "qap_swarm_stats", "qap_swarm_profile",
+           "qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_fail_alloc", "qap_swarm_live_allocations"]
 STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
@@ -82,6 +82,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_set_state.argtypes = [vp, ctypes.c_int32, P(qap_state)]
     L.qap_swarm_eval.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), ctypes.c_int32, P(ctypes.c_int64),
                                  P(ctypes.c_int64)]
+    L.qap_swarm_deltas.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_int32)]
+    L.qap_swarm_fail_alloc.argtypes = [ctypes.c_int32]
+    L.qap_swarm_live_allocations.argtypes = []
+    L.qap_swarm_live_allocations.restype = ctypes.c_int64
     L.qap_swarm_path.argtypes = [vp, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.qap_swarm_graph.argtypes = [vp, P(ctypes.c_int32), P(ctypes.c_int32)]
     L.qap_swarm_stats.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int64),
@@ -93,7 +97,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_strerror.argtypes = [ctypes.c_int]
     L.qap_swarm_strerror.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("qap_swarm_destroy", "qap_swarm_strerror"):
+        if name not in ("qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_live_allocations"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -273,6 +277,16 @@ class Swarm:
                                              _ptr(dl, ctypes.c_int64) if deltas else None), "qap_swarm_eval")
         return (goals, dl) if deltas else goals
 
+    def deltas(self, particle: int, instance: int = 0):
+        """Pair-exchange delta matrix [n, n] of the particle's S_x output in the
+        last step (before its exchanges), and that permutation."""
+        n = self.ns[instance]
+        out = np.zeros((n, n), np.int64)
+        perm = np.zeros(n, np.int32)
+        _check(load_library().qap_swarm_deltas(self.h, instance, int(particle), _ptr(out, ctypes.c_int64),
+                                               _ptr(perm, ctypes.c_int32)), "qap_swarm_deltas")
+        return out, perm
+
     def path(self, instance: int = 0):
         p = ctypes.c_int32()
         s = ctypes.c_int32()
@@ -300,11 +314,12 @@ class Swarm:
         nq = len(q)
         out = dict(swarm_q=np.zeros((m, nq), np.int64), pop_q=np.zeros(nq, np.int64),
                    swarm_hist=np.zeros((m, bins), np.int64), pop_hist=np.zeros(bins, np.int64))
-        _check(load_library().qap_swarm_stats(self.h, instance, nq, _ptr(q, ctypes.c_int32) if nq else None,
-                                              _ptr(out["swarm_q"], ctypes.c_int64), _ptr(out["pop_q"], ctypes.c_int64),
-                                              int(bins), int(lo), int(hi),
-                                              _ptr(out["swarm_hist"], ctypes.c_int64) if bins else None,
-                                              _ptr(out["pop_hist"], ctypes.c_int64) if bins else None),
+        fn = load_library().qap_swarm_stats
+        _check(fn(self.h, instance, nq, _ptr(q, ctypes.c_int32) if nq else None,
+                  _ptr(out["swarm_q"], ctypes.c_int64), _ptr(out["pop_q"], ctypes.c_int64),
+                  int(bins), int(lo), int(hi),
+                  _ptr(out["swarm_hist"], ctypes.c_int64) if bins else None,
+                  _ptr(out["pop_hist"], ctypes.c_int64) if bins else None),
                "qap_swarm_stats")
         return out
 

@@ -33,7 +33,7 @@ struct InstDesc {
     int norm;       // S_v: 0 raw, 1 column-normalised
     int depth;      // SecondTarget depth
     int sx;         // S_x procedure: 0 SecondTarget, 1 PickColumn
-    int ls;         // one pair exchange per iteration
+    int ls;         // best-improvement pair exchanges per particle-iteration (0: none)
     int migrate, migr_d, period;
     int sym;        // F and D both symmetric
     int zd;         // F and D both have a zero diagonal

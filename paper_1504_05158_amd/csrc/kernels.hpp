@@ -14,6 +14,11 @@ hipError_t launch_init(const InstDesc& d, hipStream_t st);
 // stages: ev[2s], ev[2s+1] for stage s (0 S_x, 1 velocity, 2 goal/deltas).
 hipError_t launch_plain_step(const InstDesc& d, int mul24, int grid_gd, hipStream_t st, hipEvent_t* ev);
 
+// S_x output of particle k at state tprev into out [n] (device): one wave
+// recomputes the selection the step from tprev to tprev + 1 made, from the
+// buffers of state tprev.
+hipError_t launch_sx_probe(const InstDesc& d, int k, int tprev, uint8_t* out, hipStream_t st);
+
 // Goal (+ deltas) of `count` permutations [count][n] (device) on the int32 path.
 // mode 1: eval into goals/deltas; mode 2: initial goals of the particles.
 hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, const uint8_t* perms, int count,
@@ -24,6 +29,12 @@ hipError_t launch_goal_delta_i32(const InstDesc& d, int mul24, int grid_gd, cons
 // device map workgroup -> (instance, swarm).
 hipError_t launch_bests(const InstDesc* descs, const int2* smap, int total_swarms, int count, int init,
                         hipStream_t st);
+
+// Alg. 2 for the instances descs [count] (device; whole-instance descriptors)
+// that are stepped in several stream groups: run after every group finished
+// the iteration; each instance migrates if the iteration is a multiple of its
+// period.
+hipError_t launch_migrate(const InstDesc* descs, int count, hipStream_t st);
 
 // Fused engine: one iteration of every instance of one kernel class (npad,
 // byte-split contraction, symmetric, zero diagonals) in one launch.  A class of one instance passes its

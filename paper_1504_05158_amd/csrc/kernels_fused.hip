@@ -19,6 +19,7 @@
 //       delta = A_xy + A_yx + B_xy + B_yx - (A_xx + B_xx) - (A_yy + B_yy) - kappa + lambda;
 //     the lexicographically first minimum (delta, x, y) is applied if < 0.
 //  D. X(t+1), goal, P^L.
+#include "dword.hpp"
 #include "kernels.hpp"
 #include "second_target.hpp"
 
@@ -259,21 +260,23 @@ __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF,
 __device__ __forceinline__ float clampv(float t, float vmax) { return __builtin_amdgcn_fmed3f(t, -vmax, vmax); }
 
 // Rows of X, P^L and P^G in one column and their attraction terms (velocity
-// equation) in binary64: row xr gets ox = s2 ax + s3 bx (ax, bx in {-1, 0}),
-// row lr (!= xr) ol = s2 + s3 bl (bl in {0, 1}), row gr (!= xr, lr) s3; every
-// other row none.  s2 = c2 r2 and s3 = c3 r3 are exact in binary64.
+// equation) as double words: row xr gets ox = s2 ax + s3 bx (ax, bx in
+// {-1, 0}), row lr (!= xr) ol = s2 + s3 bl (bl in {0, 1}), row gr (!= xr, lr)
+// s3; every other row none.  s2 = c2 r2 and s3 = c3 r3 are exact double words
+// (two_prod), their sum within 3u^2 of exact.
 struct Attract {
     int xr, lr, gr;
-    double ox, ol;
+    DW ox, ol;
 };
 
-// An attraction cell: c1 x + o evaluated in binary64 (c1 x is exact there) and
-// rounded once to binary32, then clamped (S_v): in binary32 the roundings of
-// c1 x and of c2 r2, c3 r3 before the terms cancel could leave an error that
-// is large next to the result.
-__device__ __forceinline__ float attract_cell(float c1, float x, double o, float vmax)
+// An attraction cell: c1 x + o with c1 x an exact double word, added to o by
+// the accurate double-word sum and rounded once to binary32, then clamped
+// (S_v).  Rounding c1 x, c2 r2 and c3 r3 separately before the terms cancel
+// could leave an error that is large next to the result; this way the result
+// is within about one unit of 2^-24 of the exact value, relative to itself.
+__device__ __forceinline__ float attract_cell(float c1, float x, DW o, float vmax)
 {
-    return clampv((float)__fma_rn((double)c1, (double)x, o), vmax);
+    return clampv(dw_add(two_prod(c1, x), o).hi, vmax);
 }
 
 // Buffer resource over one particle's n x n matrix (raw, 32-bit elements):
@@ -296,34 +299,35 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t voff, 
 // The attraction cells among rows [lo, hi) of column c: ex, el, eg are the
 // raw V(t) values at rows xr, lr, gr (read only where the row is in range).
 // Each is stored after the plain value of the same cell by the same lane
-// (program order) and replaces that value in the binary64 column sum.
+// (program order) and replaces that value in the column sum (a double word:
+// the attraction value added, the plain one taken off, both without loss).
 // X: whether the X-row cell is handled here too (else it was stored already).
 template <bool X>
 __device__ __forceinline__ void fix_cells(__amdgpu_buffer_rsrc_t rq, uint32_t col, uint32_t rowb, int lo, int hi,
                                           const Attract& at, float ex, float el, float eg, float sc, float c1,
-                                          double s3, float vmax, double& sum, float& vx)
+                                          DW s3, float vmax, DW& sum, float& vx)
 {
     if (X && at.xr >= lo && at.xr < hi) {
         const float x = __fmul_rn(ex, sc);
         vx = x;
         // no attraction term (rows of X, P^L and P^G equal): the plain value
         // stands (a re-store would cost a partial write of its line)
-        if (at.ox != 0.0) {
+        if (at.ox.hi != 0.0f) {
             const float t = attract_cell(c1, x, at.ox, vmax);
-            sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
+            sum = dw_add_f(dw_add_f(sum, fabsf(t)), -fabsf(clampv(__fmul_rn(c1, x), vmax)));
             bstore(rq, col + __umul24(at.xr, rowb), 0u, t);
         }
     }
     if (at.lr != at.xr && at.lr >= lo && at.lr < hi) {
         const float x = __fmul_rn(el, sc);
         const float t = attract_cell(c1, x, at.ol, vmax);
-        sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
+        sum = dw_add_f(dw_add_f(sum, fabsf(t)), -fabsf(clampv(__fmul_rn(c1, x), vmax)));
         bstore(rq, col + __umul24(at.lr, rowb), 0u, t);
     }
     if (at.gr != at.xr && at.gr != at.lr && at.gr >= lo && at.gr < hi) {
         const float x = __fmul_rn(eg, sc);
         const float t = attract_cell(c1, x, s3, vmax);
-        sum += (double)fabsf(t) - (double)fabsf(clampv(__fmul_rn(c1, x), vmax));
+        sum = dw_add_f(dw_add_f(sum, fabsf(t)), -fabsf(clampv(__fmul_rn(c1, x), vmax)));
         bstore(rq, col + __umul24(at.gr, rowb), 0u, t);
     }
 }
@@ -341,22 +345,25 @@ __device__ __forceinline__ void top2(float x, int u, float& m1, int& u1, float& 
 }
 
 // Column c of the velocity pass over one particle's V(t) (rp) into V(t+1)
-// before the column norm (rq): returns the sum of |.| (accumulated in
-// binary64: the attraction cells replace their plain values in it, which in
-// binary32 would leave the rounding of the larger running sum) and the column's
-// largest V(t) value m1 (first row r1), its runner-up m2, and vx = V(t) at
-// the X row.  Rows are loaded in batches so that many loads are in flight;
-// the attraction cells of a batch are read with it and fixed right after it.
+// before the column norm (rq): returns the sum of |.| rounded once from a
+// double word (each batch of 32 rows summed in binary32 as four interleaved
+// partial sums of 8, then added to the double word with the attraction-cell
+// corrections, without loss: a relative error of at most 9 units of 2^-24 at
+// any n, where one binary32 running sum could reach n - 1), and the column's
+// largest V(t) value m1
+// (first row r1), its runner-up m2, and vx = V(t) at the X row.  Rows are
+// loaded in batches so that many loads are in flight; the attraction cells of
+// a batch are read with it and fixed right after it.
 // FOLDX: the X-row cell by a select (at npad >= 128, where it costs no
 // registers), else re-stored like the others.
 template <bool FOLDX>
-__device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
-                                                float sc, float c1, double s3, float vmax, const Attract& at,
-                                                float& m1, int& r1, float& m2, float& vx)
+__device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
+                                               float sc, float c1, DW s3, float vmax, const Attract& at,
+                                               float& m1, int& r1, float& m2, float& vx)
 {
     constexpr int B = 32;
     const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)n;
-    double sum = 0.0;
+    DW sum{0.0f, 0.0f};
     int r0 = 0;
     for (; r0 + B <= n; r0 += B) {
         float v[B];
@@ -378,15 +385,17 @@ __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amd
         if (FOLDX && dx >= 0 && dx < B) vx = __fmul_rn(ex, sc);
         const float mb = m1;
         int u1 = 0;
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // rows u = 0, 1, 2, 3 mod 4
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const float x = __fmul_rn(v[u], sc);
             top2(x, u, m1, u1, m2);
             float t = clampv(__fmul_rn(c1, x), vmax);
             if constexpr (FOLDX) t = u == dx ? tx : t;
-            sum += (double)fabsf(t);
             bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
+            part[u & 3] = __fadd_rn(part[u & 3], fabsf(t));
         }
+        sum = dw_add_f(sum, __fadd_rn(__fadd_rn(part[0], part[1]), __fadd_rn(part[2], part[3])));
         r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
         fix_cells<!FOLDX>(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
@@ -398,7 +407,7 @@ __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amd
         top2(x, 0, m1, u1, m2);
         r1 = m1 != mb ? r : r1;
         const float t = clampv(__fmul_rn(c1, x), vmax);
-        sum += (double)fabsf(t);
+        sum = dw_add_f(sum, fabsf(t));
         bstore(rq, col, (uint32_t)r * rowb, t);
     }
     if (lo < n) {
@@ -407,7 +416,7 @@ __device__ __forceinline__ double stream_column(__amdgpu_buffer_rsrc_t rp, __amd
         const float eg = bload(rp, col + __umul24(at.gr >= lo ? at.gr : lo, rowb), 0u);
         fix_cells<true>(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
-    return sum;
+    return __fadd_rn(sum.hi, sum.lo);
 }
 
 }  // namespace
@@ -430,8 +439,10 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
     float* Vq = d.V[cur ^ 1] + (size_t)k * n * n;
     const uint8_t* Xk = d.X[cur] + (size_t)k * n;
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-    const double s2 = (double)d.c2 * (double)unit_float(rb.w[0]);  // exact
-    const double s3 = (double)d.c3 * (double)unit_float(rb.w[1]);
+    // c2 r2, c3 r3 (exact double words) and their sum: the attraction terms
+    const DW s2 = two_prod(d.c2, unit_float(rb.w[0]));
+    const DW s3 = two_prod(d.c3, unit_float(rb.w[1]));
+    const DW s23 = dw_add(s2, s3);
     const float c1 = d.c1, vmax = d.vmax;
 
     // ---- A. velocity stream + SecondTarget caches
@@ -449,18 +460,20 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
         const bool on = c < n;
         int xr = 0;
         float m1 = -INFINITY, m2 = -INFINITY, vx = 0.0f;
-        double sum = 0.0;
         int r1 = -1;
         if (on) {
             Attract at;
             xr = at.xr = Xk[c];
             at.lr = d.PL[(size_t)k * n + c];
             at.gr = d.PG[(size_t)gl * n + c];
-            at.ox = s2 * (double)((at.xr == at.lr) - 1) + s3 * (double)((at.xr == at.gr) - 1);
-            at.ol = s2 + s3 * (double)(at.lr == at.gr);
+            // ox = -(s2 if P^L row differs) - (s3 if P^G row differs); ol = s2 (+ s3)
+            const bool nl = at.xr != at.lr, ng = at.xr != at.gr;
+            const DW o = nl && ng ? s23 : nl ? s2 : ng ? s3 : DW{0.0f, 0.0f};
+            at.ox = dw_neg(o);
+            at.ol = at.lr == at.gr ? s23 : s2;
             const float sc = Sp[c];
-            sum = stream_column<NP >= 128>(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
-            Sq[c] = (d.norm && sum > 0.0) ? (float)(1.0 / sum) : 1.0f;
+            const float sum = stream_column<NP >= 128>(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
+            Sq[c] = (d.norm && sum > 0.0f) ? __fdiv_rn(1.0f, sum) : 1.0f;
         }
         // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
         // when the column maximum is unique and off the Z row; the runner-up

@@ -2,6 +2,7 @@
 // launches one kernel per step of the iteration with an int32 contraction for
 // the pair-exchange deltas.  The swarm-best and finish kernels are shared by
 // both engines.
+#include "dword.hpp"
 #include "kernels.hpp"
 #include "second_target.hpp"
 
@@ -28,7 +29,9 @@ __global__ void k_init_perm(InstDesc d)
     for (int j = 0; j < n; ++j) d.PL[(size_t)k * n + j] = x[j];
 }
 
-// V(0)_rc = vmax (2u - 1), then S_v; one thread per (particle, column).
+// V(0)_rc = vmax (2u - 1), then S_v; one thread per (particle, column).  The
+// column's L1 norm is accumulated as a double word (no loss per addition) and
+// rounded once, as in the velocity pass.
 __global__ void k_init_vel(InstDesc d)
 {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -37,15 +40,16 @@ __global__ void k_init_vel(InstDesc d)
     const int k = (int)(idx / n), c = (int)(idx % n);
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     float* V = d.V[0] + (size_t)k * n * n;
-    float sum = 0.0f;
+    DW sum{0.0f, 0.0f};
     for (int r = 0; r < n; ++r) {
         const float u = unit_float(stream_word(d.seed, 256u + (uint32_t)(r * n + c), 0, s, g));
         float t = __fmul_rn(d.vmax, __fsub_rn(__fmul_rn(2.0f, u), 1.0f));
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
         V[(size_t)r * n + c] = t;
-        sum = __fadd_rn(sum, fabsf(t));
+        sum = dw_add_f(sum, fabsf(t));
     }
-    d.Vinv[0][(size_t)k * n + c] = (d.norm && sum > 0.0f) ? 1.0f / sum : 1.0f;
+    const float tot = __fadd_rn(sum.hi, sum.lo);
+    d.Vinv[0][(size_t)k * n + c] = (d.norm && tot > 0.0f) ? __fdiv_rn(1.0f, tot) : 1.0f;
 }
 
 // ------------------------------------------------------------------ velocity
@@ -64,75 +68,82 @@ __global__ void k_velocity(InstDesc d)
     const int gl = k / d.S;  // swarm within this descriptor; g: within the instance
     const uint32_t g = (uint32_t)(gl + d.swarm_base), s = (uint32_t)(k % d.S);
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
-    // c2 r2, c3 r3 and c1 x are exact in binary64: an attraction cell is
-    // c1 x + s2 a + s3 b evaluated there and rounded once (the terms can
-    // cancel); the column sum is accumulated in binary64 as well
-    const double s2 = (double)d.c2 * (double)unit_float(rb.w[0]);
-    const double s3 = (double)d.c3 * (double)unit_float(rb.w[1]);
+    // c2 r2, c3 r3 and c1 x are exact double words: an attraction cell
+    // c1 x + s2 a + s3 b (a, b in {-1, 0, 1} of one sign) is summed by the
+    // accurate double-word addition and rounded once (the terms can cancel);
+    // the column sum is accumulated as a double word and rounded once
+    const DW s2 = two_prod(d.c2, unit_float(rb.w[0]));
+    const DW s3 = two_prod(d.c3, unit_float(rb.w[1]));
+    const DW s23 = dw_add(s2, s3);
     const int x = d.X[cur][(size_t)k * n + c];
     const int pl = d.PL[(size_t)k * n + c];
     const int pg = d.PG[(size_t)gl * n + c];
     const float* Vc = d.V[cur] + (size_t)k * n * n;
     const float sc = d.Vinv[cur][(size_t)k * n + c];
     float* Vn = d.V[cur ^ 1] + (size_t)k * n * n;
-    double sum = 0.0;
+    DW sum{0.0f, 0.0f};
     for (int r = 0; r < n; ++r) {
         const int a = (r == pl) - (r == x), b = (r == pg) - (r == x);
         const float v = __fmul_rn(Vc[(size_t)r * n + c], sc);
-        float t = (a | b) ? (float)__fma_rn((double)d.c1, (double)v, s2 * (double)a + s3 * (double)b)
-                          : __fmul_rn(d.c1, v);
+        float t;
+        if (a | b) {
+            const DW o = (a && b) ? s23 : a ? s2 : s3;
+            t = dw_add(two_prod(d.c1, v), (a + b) < 0 ? dw_neg(o) : o).hi;
+        } else {
+            t = __fmul_rn(d.c1, v);
+        }
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
-        sum += (double)fabsf(t);
+        sum = dw_add_f(sum, fabsf(t));
         Vn[(size_t)r * n + c] = t;
     }
-    d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && sum > 0.0) ? (float)(1.0 / sum) : 1.0f;
+    const float tot = __fadd_rn(sum.hi, sum.lo);
+    d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && tot > 0.0f) ? __fdiv_rn(1.0f, tot) : 1.0f;
 }
 
 // ------------------------------------------------------------------ S_x
+// S_x = SecondTarget of particle k at state tprev (buffers of parity tprev & 1,
+// random stream of iteration tprev + 1) into out [n]; one wave.
 template <int CPL>
-__global__ __launch_bounds__(256) void k_second_target(InstDesc d)
+__device__ __forceinline__ void second_target_particle(const InstDesc& d, int k, int tprev, uint8_t* out,
+                                                       StLds<CPL>* sl)
 {
-    __shared__ StLds<CPL> slds[4];
-    const int wave = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
-    if (wave >= d.P) return;
-    const int k = wave;
     const int n = d.n;
-    const int tprev = *d.iter;
     const int cur = tprev & 1;
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     const float* V = d.V[cur] + (size_t)k * n * n;
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     StState<CPL> st;
     st_init_scan<CPL>(n, V, Vs, d.X[cur] + (size_t)k * n, st);
-    st_select<CPL>(n, d.depth, V, Vs, st, d.Xnew + (size_t)k * n, &slds[threadIdx.x / kWave], d.seed,
-                   (uint32_t)tprev + 1u, s, g);
+    st_select<CPL>(n, d.depth, V, Vs, st, out, sl, d.seed, (uint32_t)tprev + 1u, s, g);
+}
+
+template <int CPL>
+__global__ __launch_bounds__(256) void k_second_target(InstDesc d)
+{
+    __shared__ StLds<CPL> slds[4];
+    const int wave = (int)(blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave);
+    if (wave >= d.P) return;
+    second_target_particle<CPL>(d, wave, *d.iter, d.Xnew + (size_t)wave * d.n, &slds[threadIdx.x / kWave]);
 }
 
 // S_x = PickColumn, one wave per particle: the visit order (Fisher-Yates on
 // stream elements 4 + n + j, drawn in parallel by the lanes and applied by
 // lane 0 in LDS), then per visited column the largest key over the rows left
 // (a wave maximum over lane-owned rows), equal keys to the k-th such row with
-// k = bounded(stream element 4 + visit, count).
+// k = bounded(stream element 4 + visit, count).  Particle k at state tprev
+// into out [n]; swords, order: LDS of this wave.
 template <int CPL>
-__global__ __launch_bounds__(256) void k_pick_column(InstDesc d)
+__device__ __forceinline__ void pick_column_particle(const InstDesc& d, int k, int tprev, uint8_t* out,
+                                                     uint32_t* w, uint8_t* order)
 {
-    __shared__ uint32_t swords[4][kMaxN];
-    __shared__ uint8_t sorder[4][kMaxN];
-    const int wl = (int)(threadIdx.x / kWave);
-    const int wave = (int)(blockIdx.x * (blockDim.x / kWave)) + wl;
-    if (wave >= d.P) return;
-    const int k = wave, l = lane_id();
+    const int l = lane_id();
     const int n = d.n;
-    const int tprev = *d.iter;
     const int cur = tprev & 1;
     const uint32_t tau = (uint32_t)tprev + 1u;
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
     const float* V = d.V[cur] + (size_t)k * n * n;
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     const uint8_t* z = d.X[cur] + (size_t)k * n;
-    uint8_t* out = d.Xnew + (size_t)k * n;
-    uint32_t* w = swords[wl];
-    uint8_t* order = sorder[wl];
     for (int j = l; j < n - 1; j += kWave) w[j] = stream_word(d.seed, 4u + (uint32_t)(n + j), tau, s, g);
     for (int c = l; c < n; c += kWave) order[c] = (uint8_t)c;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -196,12 +207,42 @@ __global__ __launch_bounds__(256) void k_pick_column(InstDesc d)
     }
 }
 
+
+template <int CPL>
+__global__ __launch_bounds__(256) void k_pick_column(InstDesc d)
+{
+    __shared__ uint32_t swords[4][kMaxN];
+    __shared__ uint8_t sorder[4][kMaxN];
+    const int wl = (int)(threadIdx.x / kWave);
+    const int wave = (int)(blockIdx.x * (blockDim.x / kWave)) + wl;
+    if (wave >= d.P) return;
+    pick_column_particle<CPL>(d, wave, *d.iter, d.Xnew + (size_t)wave * d.n, swords[wl], sorder[wl]);
+}
+
+// S_x output of one particle k at state tprev (one wave): the permutation the
+// step from tprev to tprev + 1 selected before its pair exchanges, recomputed
+// from the buffers of state tprev (which that step only read).
+template <int CPL>
+__global__ __launch_bounds__(64) void k_sx_probe(InstDesc d, int k, int tprev, uint8_t* out)
+{
+    __shared__ StLds<CPL> sl;
+    __shared__ uint32_t swords[kMaxN];
+    __shared__ uint8_t sorder[kMaxN];
+    if (d.sx == 1)
+        pick_column_particle<CPL>(d, k, tprev, out, swords, sorder);
+    else
+        second_target_particle<CPL>(d, k, tprev, out, &sl);
+}
+
 template __global__ void k_second_target<1>(InstDesc);
 template __global__ void k_second_target<2>(InstDesc);
 template __global__ void k_second_target<4>(InstDesc);
 template __global__ void k_pick_column<1>(InstDesc);
 template __global__ void k_pick_column<2>(InstDesc);
 template __global__ void k_pick_column<4>(InstDesc);
+template __global__ void k_sx_probe<1>(InstDesc, int, int, uint8_t*);
+template __global__ void k_sx_probe<2>(InstDesc, int, int, uint8_t*);
+template __global__ void k_sx_probe<4>(InstDesc, int, int, uint8_t*);
 
 // ------------------------------------------------------------------ goal + deltas (int32)
 // One workgroup (256 threads) per particle.  A = F . Dp^T with Dp[y][k] =
@@ -463,6 +504,45 @@ __global__ __launch_bounds__(256) void k_swarm_best(const InstDesc* __restrict__
     }
 }
 
+// ------------------------------------------------------------------ migration
+// Alg. 2 after iteration tau, one workgroup, X(tau) in buffer xb: swarms are
+// ranked by (goal of P^G, index); for q < d a uniformly drawn member of the
+// q-th best swarm gives its current solution and goal to the q-th worst swarm.
+__device__ void migrate_swarms(const InstDesc& d, int tau, int xb)
+{
+    int* __restrict__ order = d.order;
+    const int tid = threadIdx.x, n = d.n, m = d.m, S = d.S;
+    for (int g = tid; g < m; g += blockDim.x) {
+        const long long vg = d.goalPG[g];
+        int rank = 0;
+        for (int h = 0; h < m; ++h) {
+            const long long vh = d.goalPG[h];
+            rank += (vh < vg) || (vh == vg && h < g);
+        }
+        order[rank] = g;
+    }
+    __syncthreads();
+    for (int q = 0; q < d.migr_d; ++q) {
+        const int donor = order[q], recip = order[m - 1 - q];
+        const uint32_t j = bounded_u32(stream_word(d.seed, (uint32_t)q, (uint32_t)tau, 0xFFFFFFFFu, 0u), (uint32_t)S);
+        const size_t pi = (size_t)donor * S + j;
+        for (int c = tid; c < n; c += blockDim.x) d.PG[(size_t)recip * n + c] = d.X[xb][pi * n + c];
+        if (tid == 0) d.goalPG[recip] = d.goal[pi];
+    }
+}
+
+// Alg. 2 for instances stepped in several stream groups (whose own finish
+// steps do not migrate), once every group has finished iteration tau (the
+// counter the instance's descriptor points at): one workgroup per instance,
+// which acts only when tau is a multiple of its period.
+__global__ __launch_bounds__(256) void k_migrate(const InstDesc* __restrict__ descs)
+{
+    const InstDesc& d = descs[blockIdx.x];
+    const int tau = *d.iter;
+    if (d.migr_d <= 0 || tau % d.period != 0) return;
+    migrate_swarms(d, tau, tau & 1);
+}
+
 // ------------------------------------------------------------------ finish
 // One workgroup per instance (descs[blockIdx.x]): best-ever record, migration
 // (Alg. 2) when due, and the iteration counter.  Swarms are ranked by (goal of
@@ -471,7 +551,6 @@ __global__ __launch_bounds__(256) void k_swarm_best(const InstDesc* __restrict__
 __global__ __launch_bounds__(256) void k_finish(const InstDesc* __restrict__ descs, int init)
 {
     const InstDesc& d = descs[blockIdx.x];
-    int* __restrict__ order = d.order;
     __shared__ long long sg[4];
     __shared__ int ss[4];
     const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
@@ -510,26 +589,7 @@ __global__ __launch_bounds__(256) void k_finish(const InstDesc* __restrict__ des
             d.best->member = mem;
         }
     }
-    if (!init && d.migrate && d.migr_d > 0 && (tau % d.period) == 0) {
-        for (int g = tid; g < m; g += 256) {
-            const long long vg = d.goalPG[g];
-            int rank = 0;
-            for (int h = 0; h < m; ++h) {
-                const long long vh = d.goalPG[h];
-                rank += (vh < vg) || (vh == vg && h < g);
-            }
-            order[rank] = g;
-        }
-        __syncthreads();
-        for (int q = 0; q < d.migr_d; ++q) {
-            const int donor = order[q], recip = order[m - 1 - q];
-            const uint32_t j = bounded_u32(stream_word(d.seed, (uint32_t)q, (uint32_t)tau, 0xFFFFFFFFu, 0u),
-                                           (uint32_t)S);
-            const size_t pi = (size_t)donor * S + j;
-            for (int c = tid; c < n; c += 256) d.PG[(size_t)recip * n + c] = d.X[nxt][pi * n + c];
-            if (tid == 0) d.goalPG[recip] = d.goal[pi];
-        }
-    }
+    if (!init && d.migrate && d.migr_d > 0 && (tau % d.period) == 0) migrate_swarms(d, tau, nxt);
     __syncthreads();
     if (tid == 0 && !init) *d.iter = tau;
 }
@@ -567,12 +627,30 @@ hipError_t launch_bests(const InstDesc* descs, const int2* smap, int total_swarm
     return hipGetLastError();
 }
 
+hipError_t launch_migrate(const InstDesc* descs, int count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_migrate, dim3((unsigned)count), dim3(256), 0, st, descs);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const InstDesc& d, hipStream_t st)
 {
     hipLaunchKernelGGL(k_init_perm, dim3(blocks_for(d.P, 64)), dim3(64), 0, st, d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_init_vel, dim3(blocks_for((long long)d.P * d.n, 256)), dim3(256), 0, st, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_sx_probe(const InstDesc& d, int k, int tprev, uint8_t* out, hipStream_t st)
+{
+    const int cpl = d.n <= 64 ? 1 : d.n <= 128 ? 2 : 4;
+    switch (cpl) {
+    case 1: hipLaunchKernelGGL(k_sx_probe<1>, dim3(1), dim3(kWave), 0, st, d, k, tprev, out); break;
+    case 2: hipLaunchKernelGGL(k_sx_probe<2>, dim3(1), dim3(kWave), 0, st, d, k, tprev, out); break;
+    default: hipLaunchKernelGGL(k_sx_probe<4>, dim3(1), dim3(kWave), 0, st, d, k, tprev, out); break;
+    }
     return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cstdint>
 #include <cstdlib>
@@ -30,6 +31,8 @@ struct Instance {
     InstDesc d{};                 // the whole instance (iteration 0, state import/export, eval)
     int n = 0, m = 0, S = 0, P = 0;
     int mul24 = 0;
+    bool stepped = false;         // a step ran since init / set_state: the buffers of the previous state hold it
+    long long t = 0;              // completed iterations (host copy of the device counter)
     int* order = nullptr;         // [m] migration ranking scratch
     int groups = 1;               // stream groups stepping this instance
     std::vector<InstDesc> gdesc;  // [groups] descriptor of each group's swarms
@@ -68,6 +71,8 @@ struct qap_swarm {
     std::vector<hipStream_t> gstream;     // [groups]; gstream[0] = stream, the others owned
     std::vector<hipEvent_t> gevent;       // [groups]: fork (0) and joins (1..)
     std::vector<hipGraphExec_t> graphs;   // [groups] one iteration each, captured at the first step
+    std::vector<int> migr;                // instances in migration mode stepped in several groups
+    qap::InstDesc* migr_descs = nullptr;  // device [migr.size()]: their whole-instance descriptors
     hipStream_t stream = nullptr;
     bool own_stream = false;
     int engine = QAP_ENGINE_PLAIN;
@@ -86,18 +91,47 @@ struct qap_swarm {
 
 namespace {
 
+// Every device allocation of the library goes through dev_malloc / dev_free:
+// a count of the blocks held (qap_swarm_live_allocations) and the
+// allocation-failure injection of qap_swarm_fail_alloc.
+std::atomic<long long> g_live_allocs{0};
+std::atomic<long long> g_fail_countdown{0};
+
+hipError_t dev_malloc(void** p, size_t bytes)
+{
+    *p = nullptr;
+    long long c = g_fail_countdown.load();
+    while (c > 0 && !g_fail_countdown.compare_exchange_weak(c, c - 1)) {
+    }
+    if (c == 1) return hipErrorOutOfMemory;  // the injected failure
+    const hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 1);
+    if (e == hipSuccess) g_live_allocs.fetch_add(1);
+    else *p = nullptr;
+    return e;
+}
+
+void dev_free(void* p)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    g_live_allocs.fetch_sub(1);
+}
+
+// A failed allocation leaves the handle usable (nothing ran); any other
+// device error is sticky.
 int dev_err(qap_swarm* h, hipError_t e)
 {
     if (e == hipSuccess) return QAP_OK;
+    if (e == hipErrorOutOfMemory) return QAP_ERR_NOMEM;
     if (h) h->sticky = QAP_ERR_DEVICE;
-    return e == hipErrorOutOfMemory ? QAP_ERR_NOMEM : QAP_ERR_DEVICE;
+    return QAP_ERR_DEVICE;
 }
 
 template <class T>
 hipError_t dalloc(Instance& I, T** p, size_t count)
 {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 1);
+    hipError_t e = dev_malloc(&q, count * sizeof(T));
     if (e != hipSuccess) { *p = nullptr; return e; }
     I.allocs.push_back(q);
     *p = static_cast<T*>(q);
@@ -106,7 +140,7 @@ hipError_t dalloc(Instance& I, T** p, size_t count)
 
 void free_instance(Instance& I)
 {
-    for (void* p : I.allocs) (void)hipFree(p);
+    for (void* p : I.allocs) dev_free(p);
     I.allocs.clear();
 }
 
@@ -286,7 +320,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     TRY(dalloc(I, &d.PG, (size_t)I.m * n));
     TRY(dalloc(I, &d.goalPG, (size_t)I.m));
     TRY(dalloc(I, &d.smin, (size_t)I.m));
-    I.groups = (h->engine == QAP_ENGINE_FUSED && qap::fused_supported(d) && !d.migrate)
+    I.groups = (h->engine == QAP_ENGINE_FUSED && qap::fused_supported(d))
                    ? std::min(p->stream_groups > 0 ? p->stream_groups : kStreamGroups, I.m) : 1;
     TRY(dalloc(I, &d.best, (size_t)I.groups));
     TRY(dalloc(I, &d.iter, (size_t)I.groups));
@@ -328,6 +362,12 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
         gd.Xnew = d.Xnew + p0 * n;
         gd.iter = d.iter + j;
         gd.best = d.best + j;
+        // Alg. 2 ranks every swarm of the instance: with several groups it
+        // runs once all groups have finished the iteration (qap_swarm_step)
+        if (I.groups > 1) {
+            gd.migrate = 0;
+            gd.migr_d = 0;
+        }
         I.gdesc.push_back(gd);
         g0 += mj;
     }
@@ -341,7 +381,7 @@ template <class T>
 hipError_t plan_upload(StepPlan& pl, T** p, const std::vector<T>& v)
 {
     void* q = nullptr;
-    hipError_t e = hipMalloc(&q, v.size() * sizeof(T) > 0 ? v.size() * sizeof(T) : 1);
+    hipError_t e = dev_malloc(&q, v.size() * sizeof(T));
     if (e != hipSuccess) return e;
     pl.allocs.push_back(q);
     *p = static_cast<T*>(q);
@@ -351,7 +391,7 @@ hipError_t plan_upload(StepPlan& pl, T** p, const std::vector<T>& v)
 
 void free_plan(StepPlan& pl)
 {
-    for (void* p : pl.allocs) (void)hipFree(p);
+    for (void* p : pl.allocs) dev_free(p);
     pl = StepPlan();
 }
 
@@ -444,6 +484,18 @@ int build_plans(qap_swarm* h)
         }
         rc = build_plan(h, h->plans[(size_t)j], descs, own);
         if (rc != QAP_OK) return rc;
+    }
+    std::vector<qap::InstDesc> mig;
+    for (int k = 0; k < count; ++k) {
+        const Instance& I = h->inst[(size_t)k];
+        if (I.groups > 1 && I.d.migrate && I.d.migr_d > 0) {
+            h->migr.push_back(k);
+            mig.push_back(I.d);
+        }
+    }
+    if (!mig.empty()) {
+        const hipError_t e = plan_upload(h->init, &h->migr_descs, mig);
+        if (e != hipSuccess) return dev_err(nullptr, e);
     }
     h->gstream.assign(1, h->stream);
     h->graphs.assign((size_t)groups, nullptr);
@@ -640,7 +692,15 @@ void qap_swarm_destroy(qap_swarm* h)
     delete h;
 }
 
-int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count, qap_swarm** out)
+}  // extern "C"
+
+namespace {
+
+// *hold keeps the handle while it is being built, so that the entry point can
+// release it if a host allocation throws; it is cleared on every other failure
+// (the handle is released here).
+int impl_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count, qap_swarm** out,
+                    qap_swarm** hold)
 {
     if (!out) return QAP_ERR_INVALID_ARG;
     *out = nullptr;
@@ -658,12 +718,18 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     }
     qap_swarm* h = new (std::nothrow) qap_swarm();
     if (!h) return QAP_ERR_NOMEM;
+    *hold = h;
+    const auto fail = [&](int rc) {
+        qap_swarm_destroy(h);
+        *hold = nullptr;
+        return rc;
+    };
     h->engine = prms[0].engine;
-    if (hipGetDevice(&h->device) != hipSuccess) { delete h; return QAP_ERR_DEVICE; }
+    if (hipGetDevice(&h->device) != hipSuccess) return fail(QAP_ERR_DEVICE);
     if (prms[0].stream) {
         h->stream = (hipStream_t)prms[0].stream;
     } else {
-        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) { delete h; return QAP_ERR_DEVICE; }
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return fail(QAP_ERR_DEVICE);
         h->own_stream = true;
     }
     int cus = 256;
@@ -673,7 +739,7 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
     for (int k = 0; k < count; ++k) {
         const int rc = setup_instance(h, h->inst[(size_t)k], &insts[k], &prms[k], path[(size_t)k], sym[(size_t)k],
                                       mul24[(size_t)k], zd[(size_t)k], split[(size_t)k]);
-        if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
+        if (rc != QAP_OK) return fail(rc);
     }
     int rc = build_plans(h);
     if (rc == QAP_OK) {
@@ -681,17 +747,13 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
         rc = dev_err(nullptr, e);
     }
-    if (rc != QAP_OK) { qap_swarm_destroy(h); return rc; }
+    if (rc != QAP_OK) return fail(rc);
+    *hold = nullptr;
     *out = h;
     return QAP_OK;
 }
 
-int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out)
-{
-    return qap_swarm_init_batch(inst, prm, 1, out);
-}
-
-int qap_swarm_step(qap_swarm* h, int32_t iterations)
+int impl_step(qap_swarm* h, int32_t iterations)
 {
     if (!h || iterations < 0) return QAP_ERR_INVALID_ARG;
     if (h->sticky != QAP_OK) return h->sticky;
@@ -716,6 +778,28 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations)
             if (rc != QAP_OK) return rc;
         }
         if (h->profiling) h->prof_iters += 1;
+        // Alg. 2 of the instances stepped in several groups, when due: the
+        // groups join, one launch migrates, and they fork again before the
+        // next iteration reads P^G
+        bool due = false;
+        for (int k : h->migr) {
+            const Instance& I = h->inst[(size_t)k];
+            due = due || (I.t + it + 1) % I.d.period == 0;
+        }
+        if (due) {
+            for (int j = 1; j < G && e == hipSuccess; ++j) {
+                e = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
+                if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
+            }
+            if (e == hipSuccess) e = qap::launch_migrate(h->migr_descs, (int)h->migr.size(), h->stream);
+            if (e == hipSuccess) e = hipEventRecord(h->gevent[0], h->stream);
+            for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
+            if (e != hipSuccess) return dev_err(h, e);
+        }
+    }
+    for (Instance& I : h->inst) {
+        I.stepped = true;
+        I.t += iterations;
     }
     // ... and the handle's stream continues after all of them
     for (int j = 1; j < G && e == hipSuccess; ++j) {
@@ -725,7 +809,7 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations)
     return dev_err(h, e);
 }
 
-int qap_swarm_sync(qap_swarm* h)
+int impl_sync(qap_swarm* h)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
     if (h->sticky != QAP_OK) return h->sticky;
@@ -743,7 +827,7 @@ hipError_t read_best(qap_swarm* h, const Instance& I, qap::BestRec* out)
     return e;
 }
 
-int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found)
+int impl_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found)
 {
     Instance* I;
     int rc = get_instance(h, instance, &I);
@@ -758,7 +842,7 @@ int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm,
     return QAP_OK;
 }
 
-int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals)
+int impl_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals)
 {
     Instance* I;
     int rc = get_instance(h, instance, &I);
@@ -769,7 +853,7 @@ int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals)
     return dev_err(h, e);
 }
 
-int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st)
+int impl_get_state(qap_swarm* h, int32_t instance, qap_state* st)
 {
     Instance* I;
     int rc = get_instance(h, instance, &I);
@@ -821,7 +905,7 @@ int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st)
     return QAP_OK;
 }
 
-int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
+int impl_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
 {
     Instance* I;
     int rc = get_instance(h, instance, &I);
@@ -877,10 +961,12 @@ int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
     const std::vector<int> ts((size_t)I->groups, t);
     if (e == hipSuccess) e = hipMemcpy(d.best, recs.data(), sizeof(qap::BestRec) * I->groups, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d.iter, ts.data(), sizeof(int) * I->groups, hipMemcpyHostToDevice);
+    I->stepped = false;  // the previous-state buffers no longer belong to this state
+    I->t = t;
     return dev_err(h, e);
 }
 
-int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count, int64_t* goals,
+int impl_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count, int64_t* goals,
                    int64_t* deltas)
 {
     Instance* I;
@@ -903,9 +989,9 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
     uint8_t* dp = nullptr;
     long long* dg = nullptr;
     long long* dd = nullptr;
-    hipError_t e = hipMalloc(&dp, hp.size());
-    if (e == hipSuccess) e = hipMalloc(&dg, sizeof(long long) * (size_t)count);
-    if (e == hipSuccess && deltas) e = hipMalloc(&dd, sizeof(long long) * (size_t)count * n * n);
+    hipError_t e = dev_malloc(reinterpret_cast<void**>(&dp), hp.size());
+    if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&dg), sizeof(long long) * (size_t)count);
+    if (e == hipSuccess && deltas) e = dev_malloc(reinterpret_cast<void**>(&dd), sizeof(long long) * (size_t)count * n * n);
     if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), hp.size(), hipMemcpyHostToDevice, h->stream);
     if (e == hipSuccess) {
         if (qap::fused_supported(I->d))
@@ -917,13 +1003,53 @@ int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t
     if (e == hipSuccess && deltas)
         e = hipMemcpyAsync(deltas, dd, sizeof(long long) * (size_t)count * n * n, hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (dp) (void)hipFree(dp);
-    if (dg) (void)hipFree(dg);
-    if (dd) (void)hipFree(dd);
+    dev_free(dp);
+    dev_free(dg);
+    dev_free(dd);
     return dev_err(h, e);
 }
 
-int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* launches)
+int impl_deltas(qap_swarm* h, int32_t instance, int32_t particle, int64_t* out, int32_t* perm)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!out || particle < 0 || particle >= I->P || !I->stepped) return QAP_ERR_INVALID_ARG;
+    const size_t n = (size_t)I->n;
+    int t = 0;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(&t, I->d.iter, sizeof t, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_err(h, e);
+    if (t < 1) return QAP_ERR_INVALID_ARG;
+    uint8_t* dp = nullptr;
+    long long* dg = nullptr;
+    long long* dd = nullptr;
+    e = dev_malloc(reinterpret_cast<void**>(&dp), n);
+    if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&dg), sizeof(long long));
+    if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&dd), sizeof(long long) * n * n);
+    // the S_x output of the step t - 1 -> t, then its goal and deltas on the
+    // instance's contraction path
+    if (e == hipSuccess) e = qap::launch_sx_probe(I->d, particle, t - 1, dp, h->stream);
+    if (e == hipSuccess) {
+        if (qap::fused_supported(I->d))
+            e = qap::launch_eval_mfma(I->d, dp, 1, dg, dd, h->stream);
+        else
+            e = qap::launch_goal_delta_i32(I->d, I->mul24, h->grid_gd, dp, 1, 1, dg, dd, h->stream);
+    }
+    std::vector<uint8_t> hp(n);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dd, sizeof(long long) * n * n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), dp, n, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    dev_free(dp);
+    dev_free(dg);
+    dev_free(dd);
+    if (e != hipSuccess) return dev_err(h, e);
+    if (perm)
+        for (size_t j = 0; j < n; ++j) perm[j] = hp[j];
+    return QAP_OK;
+}
+
+int impl_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* launches)
 {
     if (!h || (enable != 0 && enable != 1)) return QAP_ERR_INVALID_ARG;
     if (h->sticky != QAP_OK) return h->sticky;
@@ -942,7 +1068,7 @@ int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* l
     return QAP_OK;
 }
 
-int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+int impl_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
                     int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist)
 {
     Instance* I;
@@ -973,7 +1099,7 @@ int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q
     const size_t b_out = ranks.size() * sizeof(long long), b_hist = (size_t)m * std::max(bins, 1) * 8;
     char* buf = nullptr;
     hipError_t e = hipStreamSynchronize(h->stream);
-    if (e == hipSuccess) e = hipMalloc(&buf, b_off + b_rank + b_out + b_hist);
+    if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&buf), b_off + b_rank + b_out + b_hist);
     if (e != hipSuccess) return dev_err(h, e);
     int* d_off = (int*)buf;
     long long* d_rank = (long long*)(buf + b_off);
@@ -991,7 +1117,7 @@ int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e == hipSuccess && want_q) e = hipMemcpy(outq.data(), d_out, b_out, hipMemcpyDeviceToHost);
     if (e == hipSuccess && want_h) e = hipMemcpy(hist.data(), d_hist, b_hist, hipMemcpyDeviceToHost);
-    (void)hipFree(buf);
+    dev_free(buf);
     if (e != hipSuccess) return dev_err(h, e);
     for (int j = 0; j < nq; ++j) {
         if (swarm_q)
@@ -1011,7 +1137,7 @@ int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q
     return QAP_OK;
 }
 
-int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
+int impl_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
     bool all = !h->graphs.empty();
@@ -1021,7 +1147,7 @@ int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
     return QAP_OK;
 }
 
-int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric)
+int impl_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric)
 {
     Instance* I;
     int rc = get_instance(h, instance, &I);
@@ -1030,6 +1156,175 @@ int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t*
         *delta_path = I->d.path == 1 ? QAP_PATH_INT8_MFMA : I->d.path == 3 ? QAP_PATH_SPLIT_MFMA : QAP_PATH_INT32;
     if (symmetric) *symmetric = I->d.sym;
     return QAP_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+// Entry points: no C++ exception crosses the ABI (a failed host allocation
+// is QAP_ERR_NOMEM).
+int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int32_t count, qap_swarm** out)
+{
+    qap_swarm* hold = nullptr;
+    try {
+        return impl_init_batch(insts, prms, count, out, &hold);
+    } catch (const std::bad_alloc&) {
+        qap_swarm_destroy(hold);
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        qap_swarm_destroy(hold);
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_init(const qap_instance* inst, const qap_params* prm, qap_swarm** out)
+{
+    return qap_swarm_init_batch(inst, prm, 1, out);
+}
+
+int qap_swarm_fail_alloc(int32_t nth)
+{
+    if (nth < 0) return QAP_ERR_INVALID_ARG;
+    g_fail_countdown.store(nth);
+    return QAP_OK;
+}
+
+int64_t qap_swarm_live_allocations(void) { return g_live_allocs.load(); }
+
+int qap_swarm_step(qap_swarm* h, int32_t iterations)
+{
+    try {
+        return impl_step(h, iterations);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_sync(qap_swarm* h)
+{
+    try {
+        return impl_sync(h);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_best(qap_swarm* h, int32_t instance, int64_t* goal, int32_t* perm, int32_t* iter_found)
+{
+    try {
+        return impl_best(h, instance, goal, perm, iter_found);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_swarm_bests(qap_swarm* h, int32_t instance, int64_t* goals)
+{
+    try {
+        return impl_swarm_bests(h, instance, goals);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_get_state(qap_swarm* h, int32_t instance, qap_state* st)
+{
+    try {
+        return impl_get_state(h, instance, st);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
+{
+    try {
+        return impl_set_state(h, instance, st);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_eval(qap_swarm* h, int32_t instance, const int32_t* perms, int32_t count, int64_t* goals,
+                   int64_t* deltas)
+{
+    try {
+        return impl_eval(h, instance, perms, count, goals, deltas);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_deltas(qap_swarm* h, int32_t instance, int32_t particle, int64_t* out, int32_t* perm)
+{
+    try {
+        return impl_deltas(h, instance, particle, out, perm);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_profile(qap_swarm* h, int32_t enable, double* stage_ms, int64_t* launches)
+{
+    try {
+        return impl_profile(h, enable, stage_ms, launches);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                    int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist)
+{
+    try {
+        return impl_stats(h, instance, nq, q_ppm, swarm_q, pop_q, bins, lo, hi, swarm_hist, pop_hist);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
+{
+    try {
+        return impl_graph(h, active, streams);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_path(qap_swarm* h, int32_t instance, int32_t* delta_path, int32_t* symmetric)
+{
+    try {
+        return impl_path(h, instance, delta_path, symmetric);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
 }
 
 }  // extern "C"

@@ -13,7 +13,7 @@ HEADER = os.path.join(ROOT, "include", "qap_swarm.h")
 
 def declared():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(qap_swarm_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int64_t|int|void|const char\*)\s+(qap_swarm_\w+)\s*\(", src, re.M)))
 
 
 @pytest.fixture(scope="module")

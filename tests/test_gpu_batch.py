@@ -103,20 +103,31 @@ def test_graph_replays_equal_eager(q, engine):
     b.close()
 
 
-def test_stream_groups_bit_identical(q):
-    """Independent swarms stepped as 1, 2 or 3 concurrent stream groups give
-    identical states: the groups only partition the swarms."""
+@pytest.mark.parametrize("migration", [False, True], ids=["independent", "migration"])
+def test_stream_groups_bit_identical(q, migration):
+    """Swarms stepped as 1, 2 or 3 concurrent stream groups give identical
+    states: the groups only partition the swarms.  In migration mode the
+    groups join at every iteration where Alg. 2 is due and one launch ranks
+    all swarms of the instance (period 3 here: several migrations in the run,
+    and steps that end on, before and after one)."""
     F, D = gen.uniform_instance(64, 0, 99, 31)
-    cfg = run_cfg(num_swarms=7, particles_per_swarm=9, seed=17)
-    announce("stream groups")
+    cfg = run_cfg(num_swarms=7, particles_per_swarm=9, seed=17, migration=migration,
+                  migration_factor=0.3 if migration else 0.0, migration_period=3 if migration else 1)
+    announce("stream groups", migration)
     hs = [q.Swarm.create(F, D, engine="fused", stream_groups=g, **cfg) for g in (1, 2, 3)]
     assert [h.stream_groups() for h in hs] == [1, 2, 3]
-    for it in range(4):
+    moved = 0
+    for it in range(5):
+        before = hs[0].get_state()
         for h in hs:
             h.step(1 + it)
         ref = hs[0].get_state()
         for h in hs[1:]:
             assert_same(h.get_state(), ref, ("groups", h.stream_groups(), "after", it + 1))
             assert h.best()[0] == hs[0].best()[0]
+        best_now = ref["goal"].reshape(7, 9).min(axis=1)
+        moved += int((ref["goalPG"] != np.minimum(before["goalPG"], best_now)).sum())
+    if migration:
+        assert moved > 0  # Alg. 2 moved solutions within the run
     for h in hs:
         h.close()

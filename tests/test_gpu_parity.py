@@ -1,7 +1,7 @@
 """GPU parity: the HIP library (through the C ABI) against the CPU oracle.
 
 Goals, pair-exchange deltas and every permutation are compared exactly;
-velocities within 1e-5 of each column's largest entry (FP32 vs FP64).  One
+velocities entry by entry within 1e-5 relative (FP32 vs FP64).  One
 step is compared from the same state: the GPU's state is exported, loaded into
 the oracle, and both advance one iteration.
 """
@@ -48,10 +48,13 @@ def test_eval_goals_and_deltas_exact(q, orc, engine, name, mk):
 
 @pytest.mark.parametrize("engine", ENGINES)
 @pytest.mark.parametrize("norm", [True, False])
-def test_init_parity(q, orc, engine, norm):
-    F, D = gen.uniform_instance(20, 0, 50, 11)
+@pytest.mark.parametrize("n", [20, 128, 150, 256])
+def test_init_parity(q, orc, engine, norm, n):
+    """Iteration 0 (random permutations, V(0) through S_v, goals, bests) up to
+    the largest size: the column norm of V(0) sums n entries."""
+    F, D = gen.uniform_instance(n, 0, 50, 11)
     cfg = run_cfg(num_swarms=3, particles_per_swarm=17, norm=norm, vmax=0.8, seed=99)
-    announce("init", engine, norm)
+    announce("init", engine, norm, n)
     sw = make_gpu(q, F, D, dict(cfg, engine=engine))
     g = sw.get_state()
     o = orc.OracleSwarm(F, D, **cfg).state()
