@@ -246,6 +246,23 @@ enum { QAP_STATS_MAX_RANKS = 64, QAP_STATS_MAX_BINS = 4096 };
 int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
                     int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist);
 
+/* qap_swarm_stats for callers that cannot allocate memory (code under graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments and results, computed without any device or host allocation.
+ * Its scratch (segment offsets, ranks, selected values, bin counts) lives in
+ * a fixed device array of QAP_STATS_SCRATCH_BYTES, one per GPU, set up at the
+ * first init on that GPU and held until the process ends.  A request needing
+ * more -- 4 (m + 3) + 16 (m + 1) max(nq, 1) + 8 (m + 1) max(bins, 1) bytes,
+ * each of the four parts rounded up to 256 -- returns QAP_ERR_UNSUPPORTED
+ * (qap_swarm_stats has no such limit).  Every call on one GPU uses the same
+ * array, which keeps the last call's contents: calls that overlap in time on
+ * one GPU (from other threads or on other handles' streams) race, and the
+ * library does not serialise them.  Waits for the result. */
+enum { QAP_STATS_SCRATCH_BYTES = 4194304 };
+int qap_swarm_stats_noalloc(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                            int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist,
+                            int64_t* pop_hist);
+
 /* Kernel timing for measurement (runtime; no passage of the paper).
  * enable = 1 switches the handle to
  * profiled stepping: every later qap_swarm_step launches its kernels one by

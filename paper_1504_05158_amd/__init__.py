@@ -31,7 +31,8 @@ QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
            "qap_swarm_deltas", "qap_swarm_path", "qap_swarm_graph", "qap_swarm_stats", "qap_swarm_profile",
-           "qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_fail_alloc", "qap_swarm_live_allocations"]
+           "qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_fail_alloc", "qap_swarm_live_allocations",
+           "qap_swarm_stats_noalloc"]
 STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
@@ -91,6 +92,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.qap_swarm_stats.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int64),
                                   P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                   P(ctypes.c_int64), P(ctypes.c_int64)]
+    L.qap_swarm_stats_noalloc.argtypes = L.qap_swarm_stats.argtypes
     L.qap_swarm_profile.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     L.qap_swarm_destroy.argtypes = [vp]
     L.qap_swarm_destroy.restype = None
@@ -306,21 +308,22 @@ class Swarm:
         return int(g.value)
 
     def stats(self, q_ppm=(50000, 250000, 500000, 750000), bins: int = 0, lo: int = 0, hi: int = 1,
-              instance: int = 0) -> dict:
+              instance: int = 0, noalloc: bool = False) -> dict:
         """Percentile ranks (nearest rank, q in parts per million) and PMF counts of
-        the current goals, per swarm and over the population."""
+        the current goals, per swarm and over the population.  noalloc: through
+        qap_swarm_stats_noalloc (fixed scratch, no allocation)."""
         m = self.ms[instance]
         q = np.ascontiguousarray(q_ppm, np.int32)
         nq = len(q)
         out = dict(swarm_q=np.zeros((m, nq), np.int64), pop_q=np.zeros(nq, np.int64),
                    swarm_hist=np.zeros((m, bins), np.int64), pop_hist=np.zeros(bins, np.int64))
-        fn = load_library().qap_swarm_stats
+        fn = load_library().qap_swarm_stats_noalloc if noalloc else load_library().qap_swarm_stats
         _check(fn(self.h, instance, nq, _ptr(q, ctypes.c_int32) if nq else None,
                   _ptr(out["swarm_q"], ctypes.c_int64), _ptr(out["pop_q"], ctypes.c_int64),
                   int(bins), int(lo), int(hi),
                   _ptr(out["swarm_hist"], ctypes.c_int64) if bins else None,
                   _ptr(out["pop_hist"], ctypes.c_int64) if bins else None),
-               "qap_swarm_stats")
+               "qap_swarm_stats_noalloc" if noalloc else "qap_swarm_stats")
         return out
 
     def profile(self, enable: bool):

@@ -71,4 +71,14 @@ hipError_t launch_select(const long long* values, const int* seg_off, int nseg, 
 hipError_t launch_hist(const long long* values, const int* seg_off, int nseg, int bins, long long lo, long long hi,
                        unsigned long long* out, hipStream_t st);
 
+// The ranks of a statistics request in parts per million (passed by value).
+constexpr int kStatsMaxRanks = 64;
+struct StatsRanks {
+    int ppm[kStatsMaxRanks];
+};
+
+// seg_off [m + 3] and ranks [(m + 1) nq] of a request (see k_stats_setup).
+hipError_t launch_stats_setup(int* seg_off, long long* ranks, int m, int S, int P, int nq, const StatsRanks& q,
+                              hipStream_t st);
+
 }  // namespace qap

@@ -70,6 +70,34 @@ __global__ __launch_bounds__(256) void k_hist(const long long* __restrict__ valu
     for (int i = threadIdx.x; i < bins; i += blockDim.x) out[(size_t)seg * bins + i] = hist[i];
 }
 
+// Segment offsets and ranks of a statistics request, written on the device:
+// seg_off [m + 3] = (0, S, .., m S) for the m swarms, then (0, P) for the
+// population; ranks [(m + 1) nq] = max(1, ceil(q_j N / 10^6)) with N = S for
+// the swarms and P for the population.
+__global__ void k_stats_setup(int* __restrict__ seg_off, long long* __restrict__ ranks, int m, int S, int P, int nq,
+                              StatsRanks q)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i <= m) seg_off[i] = i * S;
+    if (i == m + 1) seg_off[i] = 0;
+    if (i == m + 2) seg_off[i] = P;
+    if (i < (m + 1) * nq) {
+        const int g = i / nq, j = i % nq;
+        const long long N = g < m ? S : P;
+        const long long r = ((long long)q.ppm[j] * N + 999999) / 1000000;
+        ranks[i] = r > 1 ? r : 1;
+    }
+}
+
+hipError_t launch_stats_setup(int* seg_off, long long* ranks, int m, int S, int P, int nq, const StatsRanks& q,
+                              hipStream_t st)
+{
+    const long long items = (long long)(m + 3) > (long long)(m + 1) * nq ? (long long)(m + 3) : (long long)(m + 1) * nq;
+    hipLaunchKernelGGL(k_stats_setup, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, st, seg_off, ranks, m, S, P,
+                       nq, q);
+    return hipGetLastError();
+}
+
 hipError_t launch_select(const long long* values, const int* seg_off, int nseg, const long long* ranks, int nr,
                          long long* out, hipStream_t st)
 {

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <mutex>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -75,6 +76,7 @@ struct qap_swarm {
     qap::InstDesc* migr_descs = nullptr;  // device [migr.size()]: their whole-instance descriptors
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    void* scratch = nullptr;              // device address of the stats scratch array on this device
     int engine = QAP_ENGINE_PLAIN;
     int sticky = QAP_OK;
     int grid_gd = 0;
@@ -115,6 +117,34 @@ void dev_free(void* p)
     if (!p) return;
     (void)hipFree(p);
     g_live_allocs.fetch_sub(1);
+}
+
+// Scratch of qap_swarm_stats_noalloc: a fixed device array (each GPU holds
+// its own copy until the process ends).  In host code the name `scratch` is a
+// host-side stand-in; the device address is taken once per device, with that
+// device current, by hipGetSymbolAddress at the first init on the device, and
+// only that address is used from then on.
+constexpr size_t kScratchBytes = QAP_STATS_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+hipError_t scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 // A failed allocation leaves the handle usable (nothing ran); any other
@@ -726,6 +756,7 @@ int impl_init_batch(const qap_instance* insts, const qap_params* prms, int32_t c
     };
     h->engine = prms[0].engine;
     if (hipGetDevice(&h->device) != hipSuccess) return fail(QAP_ERR_DEVICE);
+    if (scratch_address(h->device, &h->scratch) != hipSuccess) return fail(QAP_ERR_DEVICE);
     if (prms[0].stream) {
         h->stream = (hipStream_t)prms[0].stream;
     } else {
@@ -1137,6 +1168,62 @@ int impl_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm,
     return QAP_OK;
 }
 
+// qap_swarm_stats with its scratch in the fixed device array: the request's
+// segment offsets and ranks are written by a kernel, the selections and bin
+// counts land in the array, and the results are copied from it into the
+// caller's arrays.  No allocation, device or host.
+int impl_stats_noalloc(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                       int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (nq < 0 || nq > QAP_STATS_MAX_RANKS || (nq > 0 && !q_ppm)) return QAP_ERR_INVALID_ARG;
+    for (int j = 0; j < nq; ++j)
+        if (q_ppm[j] < 1 || q_ppm[j] > 1000000) return QAP_ERR_INVALID_ARG;
+    if (bins < 0 || bins > QAP_STATS_MAX_BINS) return QAP_ERR_INVALID_ARG;
+    if (bins > 0 && (!(lo < hi) || (unsigned long long)hi - (unsigned long long)lo > (1ull << 62) / (unsigned)bins))
+        return QAP_ERR_INVALID_ARG;
+    const bool want_q = nq > 0 && (swarm_q || pop_q), want_h = bins > 0 && (swarm_hist || pop_hist);
+    if (!want_q && !want_h) return QAP_OK;
+    if (!h->scratch) return QAP_ERR_DEVICE;
+    const int m = I->m, S = I->S, P = I->P;
+    const auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t b_off = up(sizeof(int) * (size_t)(m + 3));
+    const size_t b_rank = up(sizeof(long long) * (size_t)(m + 1) * (size_t)std::max(nq, 1));
+    const size_t b_hist = up(sizeof(long long) * (size_t)(m + 1) * (size_t)std::max(bins, 1));
+    if (b_off + 2 * b_rank + b_hist > kScratchBytes) return QAP_ERR_UNSUPPORTED;
+    char* base = static_cast<char*>(h->scratch);
+    int* d_off = reinterpret_cast<int*>(base);
+    long long* d_rank = reinterpret_cast<long long*>(base + b_off);
+    long long* d_out = reinterpret_cast<long long*>(base + b_off + b_rank);
+    unsigned long long* d_hist = reinterpret_cast<unsigned long long*>(base + b_off + 2 * b_rank);
+    qap::StatsRanks qr{};
+    for (int j = 0; j < nq; ++j) qr.ppm[j] = q_ppm[j];
+    hipStream_t st = h->stream;
+    const long long* goals = I->d.goal;
+    hipError_t e = qap::launch_stats_setup(d_off, d_rank, m, S, P, want_q ? nq : 0, qr, st);
+    if (e == hipSuccess && want_q) e = qap::launch_select(goals, d_off, m, d_rank, nq, d_out, st);
+    if (e == hipSuccess && want_q)
+        e = qap::launch_select(goals, d_off + m + 1, 1, d_rank + (size_t)m * nq, nq, d_out + (size_t)m * nq, st);
+    if (e == hipSuccess && want_h) e = qap::launch_hist(goals, d_off, m, bins, lo, hi, d_hist, st);
+    if (e == hipSuccess && want_h)
+        e = qap::launch_hist(goals, d_off + m + 1, 1, bins, lo, hi, d_hist + (size_t)m * bins, st);
+    // nq >= 1 here, so the selections are [m + 1][nq] in the caller's order;
+    // counts are below 2^63, so the unsigned words are the int64 values
+    if (e == hipSuccess && want_q && swarm_q)
+        e = hipMemcpyAsync(swarm_q, d_out, sizeof(long long) * (size_t)m * nq, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && want_q && pop_q)
+        e = hipMemcpyAsync(pop_q, d_out + (size_t)m * nq, sizeof(long long) * (size_t)nq, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && want_h && swarm_hist)
+        e = hipMemcpyAsync(swarm_hist, d_hist, sizeof(long long) * (size_t)m * bins, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && want_h && pop_hist)
+        e = hipMemcpyAsync(pop_hist, d_hist + (size_t)m * bins, sizeof(long long) * (size_t)bins,
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return dev_err(h, e);
+}
+
 int impl_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
@@ -1300,6 +1387,17 @@ int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q
         return impl_stats(h, instance, nq, q_ppm, swarm_q, pop_q, bins, lo, hi, swarm_hist, pop_hist);
     } catch (const std::bad_alloc&) {
         return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_stats_noalloc(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
+                            int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist,
+                            int64_t* pop_hist)
+{
+    try {
+        return impl_stats_noalloc(h, instance, nq, q_ppm, swarm_q, pop_q, bins, lo, hi, swarm_hist, pop_hist);
     } catch (...) {
         return QAP_ERR_DEVICE;
     }
