@@ -73,6 +73,28 @@ struct InstDesc {
     int* scratch;           // per-block contraction scratch (per-stage engine)
 };
 
+// A pointer read from device memory (a descriptor in a device table) is
+// generic to the compiler, so accesses through it become flat instructions
+// (64-bit addresses in vector registers, and waits shared with LDS).  Every
+// pointer of a descriptor is device global memory: accesses through gl(p)
+// are global instructions.
+template <class T>
+using global_t = __attribute__((address_space(1))) T;
+
+template <class T>
+__device__ __forceinline__ global_t<T>* gl(T* p)
+{
+    return (global_t<T>*)p;
+}
+
+// Buffer b (0 or 1) of a double-buffered member, chosen by a select rather
+// than an index: a descriptor held in registers then stays in registers.
+template <class T>
+__device__ __forceinline__ T* buf(T* const (&a)[2], int b)
+{
+    return b ? a[1] : a[0];
+}
+
 // ---------------------------------------------------------------- wave ops
 // The lane id goes through an empty asm so that values derived from it are
 // formed where used rather than hoisted out of a long loop (where they would

@@ -243,15 +243,15 @@ template <int NP, bool SYM>
 __device__ __forceinline__ void load_instance_lds(const InstDesc& d, int8_t* sF, int8_t* sD, int8_t* sFT, int8_t* sDT)
 {
     constexpr int LS = lds_stride<NP>(), LSD = lds_stride_d<NP>(), RV = NP / 16;  // 16-byte chunks per row
-    const v4i* F = reinterpret_cast<const v4i*>(d.F8);
-    const v4i* D = reinterpret_cast<const v4i*>(d.D8);
+    global_t<const v4i>* F = reinterpret_cast<global_t<const v4i>*>(gl(d.F8));
+    global_t<const v4i>* D = reinterpret_cast<global_t<const v4i>*>(gl(d.D8));
     for (int i = threadIdx.x; i < NP * RV; i += blockDim.x) {
         const int o = (i / RV) * LS + 16 * (i % RV), od = (i / RV) * LSD + 16 * (i % RV);
         *reinterpret_cast<v4i*>(sF + o) = F[i];
         *reinterpret_cast<v4i*>(sD + od) = D[i];
         if constexpr (!SYM) {
-            *reinterpret_cast<v4i*>(sFT + o) = reinterpret_cast<const v4i*>(d.FT8)[i];
-            *reinterpret_cast<v4i*>(sDT + od) = reinterpret_cast<const v4i*>(d.DT8)[i];
+            *reinterpret_cast<v4i*>(sFT + o) = reinterpret_cast<global_t<const v4i>*>(gl(d.FT8))[i];
+            *reinterpret_cast<v4i*>(sDT + od) = reinterpret_cast<global_t<const v4i>*>(gl(d.DT8))[i];
         }
     }
 }
@@ -399,22 +399,37 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
         r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
         fix_cells<!FOLDX>(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
-    const int lo = r0;
-    for (int r = r0; r < n; ++r) {
-        const float x = __fmul_rn(bload(rp, col, (uint32_t)r * rowb), sc);
+    if (r0 < n) {
+        // the last rows, fewer than a batch, as one more batch: all loads are
+        // issued together (row indices clamped to the matrix), the rows past
+        // n skipped by uniform branches
+        const int valid = n - r0;
+        float v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)min(r0 + u, n - 1) * rowb);
+        const float ex = bload(rp, col + __umul24(at.xr >= r0 ? at.xr : r0, rowb), 0u);
+        const float el = bload(rp, col + __umul24(at.lr >= r0 ? at.lr : r0, rowb), 0u);
+        const float eg = bload(rp, col + __umul24(at.gr >= r0 ? at.gr : r0, rowb), 0u);
+        const float tx = attract_cell(c1, __fmul_rn(ex, sc), at.ox, vmax);
+        const int dx = FOLDX ? at.xr - r0 : -1;
+        if (FOLDX && dx >= 0) vx = __fmul_rn(ex, sc);
         const float mb = m1;
         int u1 = 0;
-        top2(x, 0, m1, u1, m2);
-        r1 = m1 != mb ? r : r1;
-        const float t = clampv(__fmul_rn(c1, x), vmax);
-        sum = dw_add_f(sum, fabsf(t));
-        bstore(rq, col, (uint32_t)r * rowb, t);
-    }
-    if (lo < n) {
-        const float ex = bload(rp, col + __umul24(at.xr >= lo ? at.xr : lo, rowb), 0u);
-        const float el = bload(rp, col + __umul24(at.lr >= lo ? at.lr : lo, rowb), 0u);
-        const float eg = bload(rp, col + __umul24(at.gr >= lo ? at.gr : lo, rowb), 0u);
-        fix_cells<true>(rq, col, rowb, lo, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
+        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (u < valid) {
+                const float x = __fmul_rn(v[u], sc);
+                top2(x, u, m1, u1, m2);
+                float t = clampv(__fmul_rn(c1, x), vmax);
+                if constexpr (FOLDX) t = u == dx ? tx : t;
+                bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
+                part[u & 3] = __fadd_rn(part[u & 3], fabsf(t));
+            }
+        }
+        sum = dw_add_f(sum, __fadd_rn(__fadd_rn(part[0], part[1]), __fadd_rn(part[2], part[3])));
+        r1 = m1 != mb ? r0 + u1 : r1;
+        fix_cells<!FOLDX>(rq, col, rowb, r0, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
     return __fadd_rn(sum.hi, sum.lo);
 }
@@ -430,14 +445,14 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
 {
     const int l = lane_id();
     const int n = d.n;
-    const int tprev = *d.iter;
+    const int tprev = *gl(d.iter);
     const uint32_t tau = (uint32_t)tprev + 1u;
     const int cur = tprev & 1;
-    const int gl = k / d.S;  // swarm within this descriptor; g: within the instance
-    const uint32_t g = (uint32_t)(gl + d.swarm_base), s = (uint32_t)(k % d.S);
-    const float* Vp = d.V[cur] + (size_t)k * n * n;
-    float* Vq = d.V[cur ^ 1] + (size_t)k * n * n;
-    const uint8_t* Xk = d.X[cur] + (size_t)k * n;
+    const int gs = k / d.S;  // swarm within this descriptor; g: within the instance
+    const uint32_t g = (uint32_t)(gs + d.swarm_base), s = (uint32_t)(k % d.S);
+    global_t<const float>* Vp = gl(buf(d.V, cur)) + (size_t)k * n * n;
+    float* Vq = buf(d.V, cur ^ 1) + (size_t)k * n * n;  // buffer stores
+    global_t<const uint8_t>* Xk = gl(buf(d.X, cur)) + (size_t)k * n;
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
     // c2 r2, c3 r3 (exact double words) and their sum: the attraction terms
     const DW s2 = two_prod(d.c2, unit_float(rb.w[0]));
@@ -446,9 +461,9 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
     const float c1 = d.c1, vmax = d.vmax;
 
     // ---- A. velocity stream + SecondTarget caches
-    const float* Sp = d.Vinv[cur] + (size_t)k * n;
-    float* Sq = d.Vinv[cur ^ 1] + (size_t)k * n;
-    const __amdgpu_buffer_rsrc_t rp = matrix_rsrc(Vp, n), rq = matrix_rsrc(Vq, n);
+    global_t<const float>* Sp = gl(buf(d.Vinv, cur)) + (size_t)k * n;
+    global_t<float>* Sq = gl(buf(d.Vinv, cur ^ 1)) + (size_t)k * n;
+    const __amdgpu_buffer_rsrc_t rp = matrix_rsrc((const float*)Vp, n), rq = matrix_rsrc(Vq, n);
     StState<CPL> st;
     st.rowbits = 0;
 #pragma unroll
@@ -464,8 +479,8 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
         if (on) {
             Attract at;
             xr = at.xr = Xk[c];
-            at.lr = d.PL[(size_t)k * n + c];
-            at.gr = d.PG[(size_t)gl * n + c];
+            at.lr = gl(d.PL)[(size_t)k * n + c];
+            at.gr = gl(d.PG)[(size_t)gs * n + c];
             // ox = -(s2 if P^L row differs) - (s3 if P^G row differs); ol = s2 (+ s3)
             const bool nl = at.xr != at.lr, ng = at.xr != at.gr;
             const DW o = nl && ng ? s23 : nl ? s2 : ng ? s3 : DW{0.0f, 0.0f};
@@ -537,18 +552,20 @@ __device__ __forceinline__ void write_particle(const InstDesc& d, int k, int cur
                                                int ba, int bb)
 {
     const int n = d.n, l = lane_id();
-    uint8_t* Xo = d.X[cur ^ 1] + (size_t)k * n;
-    const bool improve = goal < d.goalPL[k];
+    global_t<uint8_t>* Xo = gl(buf(d.X, cur ^ 1)) + (size_t)k * n;
+    global_t<uint8_t>* PL = gl(d.PL);
+    global_t<long long>* gpl = gl(d.goalPL);
+    const bool improve = goal < gpl[k];
     for (int j = l; j < n; j += kWave) {
         uint8_t v = pw[j];
         if (j == ba) v = pw[bb];
         if (j == bb) v = pw[ba];
         Xo[j] = v;
-        if (improve) d.PL[(size_t)k * n + j] = v;
+        if (improve) PL[(size_t)k * n + j] = v;
     }
     if (l == 0) {
-        d.goal[k] = goal;
-        if (improve) d.goalPL[k] = goal;
+        gl(d.goal)[k] = goal;
+        if (improve) gpl[k] = goal;
     }
 }
 
@@ -556,15 +573,14 @@ template <int NP>
 constexpr int cols_per_lane() { return NP <= 64 ? 1 : NP <= 128 ? 2 : 4; }
 
 // TABLE: workgroup b steps particles blkmap[b].y .. +3 of instance
-// descs[blkmap[b].x]; otherwise workgroup b steps particles 4b .. 4b+3 of the
-// instance passed as `one` (a kernel argument, whose pointers the compiler
-// knows to be global: accesses through them avoid flat instructions).
-template <int NP, bool SYM, bool ZD, bool TABLE>
-__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
-                                                    const int2* __restrict__ blkmap)
+// descs[blkmap[b].x] (its pointers marked global where they are used, see
+// gl); otherwise
+// workgroup b steps particles 4b .. 4b+3 of the instance passed as `one` (a
+// kernel argument, whose pointers the compiler knows to be global).
+// One workgroup of k_fused_step: particles first .. first + 3 of d.
+template <int NP, bool SYM, bool ZD>
+__device__ __forceinline__ void fused_step_block(const InstDesc& d, int first)
 {
-    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
-    const InstDesc& d = TABLE ? descs[bm.x] : one;
     constexpr int CPL = cols_per_lane<NP>();  // column slots per lane
     __shared__ __attribute__((aligned(16))) int8_t sF[NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride_d<NP>()];
@@ -582,7 +598,7 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
 
     // wave index made explicitly uniform: every per-particle address lives in scalar registers
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int k = bm.y + w;
+    const int k = first + w;
     if (k >= d.P) return;
     uint8_t* pw = sp[w];
     const int cur = velocity_and_target<NP, CPL>(d, k, pw, &sws[w].st);
@@ -592,6 +608,18 @@ __global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc
         goal_delta_mfma<NP, SYM, ZD>(d.n, sF, sD, sFT, sDT, pw, sws[w].ri, d.ls != 0, nullptr, g, key);
     }, goal, ba, bb);
     write_particle(d, k, cur, pw, goal, ba, bb);
+}
+
+template <int NP, bool SYM, bool ZD, bool TABLE>
+__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
+                                                    const int2* __restrict__ blkmap)
+{
+    if constexpr (TABLE) {
+        const int2 bm = blkmap[blockIdx.x];
+        fused_step_block<NP, SYM, ZD>(descs[__builtin_amdgcn_readfirstlane(bm.x)], __builtin_amdgcn_readfirstlane(bm.y));
+    } else {
+        fused_step_block<NP, SYM, ZD>(one, (int)blockIdx.x * kWaves);
+    }
 }
 
 // ------------------------------------------------------------------ wide step
@@ -631,8 +659,8 @@ template <int NP>
 __device__ __forceinline__ void load_wide_lds(const InstDesc& d, int8_t* pl)
 {
     constexpr int LS = lds_stride<NP>(), PS = NP * LS, RV = NP / 16;
-    const v4i* src[4] = {reinterpret_cast<const v4i*>(d.F8), reinterpret_cast<const v4i*>(d.FH8),
-                         reinterpret_cast<const v4i*>(d.D8), reinterpret_cast<const v4i*>(d.DH8)};
+    global_t<const v4i>* src[4] = {reinterpret_cast<global_t<const v4i>*>(gl(d.F8)), reinterpret_cast<global_t<const v4i>*>(gl(d.FH8)),
+                                   reinterpret_cast<global_t<const v4i>*>(gl(d.D8)), reinterpret_cast<global_t<const v4i>*>(gl(d.DH8))};
     const bool on[4] = {true, (d.split & 1) != 0, true, (d.split & 2) != 0};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
@@ -810,12 +838,9 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
     bestkey = wave_min_i64(bestkey);
 }
 
-template <int NP, bool ZD, bool HS, bool TABLE>
-__global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
-                                                    const int2* __restrict__ blkmap)
+template <int NP, bool ZD, bool HS>
+__device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
 {
-    const int2 bm = TABLE ? blkmap[blockIdx.x] : make_int2(0, (int)blockIdx.x * kWaves);
-    const InstDesc& d = TABLE ? descs[bm.x] : one;
     constexpr int CPL = cols_per_lane<NP>();
     __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[kWaves];
@@ -823,7 +848,7 @@ __global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc
     __syncthreads();
 
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int k = bm.y + w;
+    const int k = first + w;
     if (k >= d.P) return;
     uint8_t* pw = sw[w].p;
     const int cur = velocity_and_target<NP, CPL>(d, k, pw, &sw[w].u.st);
@@ -834,6 +859,18 @@ __global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc
         goal_delta_wide<NP, ZD, HS>(d.n, d.split, spl, pw, sw[w].q, sw[w].u.ri, d.ls != 0, nullptr, g, key);
     }, goal, ba, bb);
     write_particle(d, k, cur, pw, goal, ba, bb);
+}
+
+template <int NP, bool ZD, bool HS, bool TABLE>
+__global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
+                                                    const int2* __restrict__ blkmap)
+{
+    if constexpr (TABLE) {
+        const int2 bm = blkmap[blockIdx.x];
+        fused_wide_block<NP, ZD, HS>(descs[__builtin_amdgcn_readfirstlane(bm.x)], __builtin_amdgcn_readfirstlane(bm.y));
+    } else {
+        fused_wide_block<NP, ZD, HS>(one, (int)blockIdx.x * kWaves);
+    }
 }
 
 // ------------------------------------------------------------------ eval

@@ -38,8 +38,8 @@ struct StState {
 };
 
 // Exact best non-Z key of column c over the alive rows (whole wave).
-template <int CPL>
-__device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, const float* __restrict__ Vs, int c,
+template <int CPL, class PV>
+__device__ __forceinline__ void st_rescan(int n, PV __restrict__ V, PV __restrict__ Vs, int c,
                                           int zr, unsigned rowbits, float& mv, int& mr, int& mc)
 {
     const int l = lane_id();
@@ -68,8 +68,8 @@ __device__ __forceinline__ void st_rescan(int n, const float* __restrict__ V, co
 }
 
 // Row of the k-th tied cell (ascending row) of column c with key m.
-template <int CPL>
-__device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ V, const float* __restrict__ Vs,
+template <int CPL, class PV>
+__device__ __forceinline__ int st_kth_tied_row(int n, PV __restrict__ V, PV __restrict__ Vs,
                                                int c, int zr, bool withZ, unsigned rowbits, float m, int k)
 {
     const int l = lane_id();
@@ -97,8 +97,8 @@ __device__ __forceinline__ int st_kth_tied_row(int n, const float* __restrict__ 
 }
 
 // Initial per-column cache by a full scan of V (exact, not stale).
-template <int CPL>
-__device__ __forceinline__ void st_init_scan(int n, const float* __restrict__ V, const float* __restrict__ Vs,
+template <int CPL, class PV>
+__device__ __forceinline__ void st_init_scan(int n, PV __restrict__ V, PV __restrict__ Vs,
                                              const uint8_t* __restrict__ z, StState<CPL>& s)
 {
     const int l = lane_id();
@@ -241,8 +241,8 @@ __device__ int st_tie_run(int n, int i, StState<CPL>& s, bool (&tz)[CPL], bool (
 // out and the dead flags, cal cleared), *group = their number, and the
 // return value is -1.  The per-lane state other than cal is then stale until
 // st_sync.
-template <int CPL, class L>
-__device__ int st_generic_pick(int n, int i, bool skipZ, const float* __restrict__ V, const float* __restrict__ Vs,
+template <int CPL, class L, class PV>
+__device__ int st_generic_pick(int n, int i, bool skipZ, PV __restrict__ V, PV __restrict__ Vs,
                                StState<CPL>& s, uint64_t seed, uint32_t iter, uint32_t member, uint32_t swarm,
                                int& selr, L* lds = nullptr, uint8_t* out = nullptr, int* group = nullptr)
 {
@@ -443,8 +443,8 @@ __device__ __forceinline__ float st_nonz_bound(const StState<CPL>& s)
 // selection after them (a non-Z cell or a Z cell not above the bound) uses
 // the exact procedure, then the bound is recomputed and the next group taken.
 // lds: the wave's scratch.
-template <int CPL>
-__device__ void st_select(int n, int depth, const float* __restrict__ V, const float* __restrict__ Vs,
+template <int CPL, class PV>
+__device__ void st_select(int n, int depth, PV __restrict__ V, PV __restrict__ Vs,
                           StState<CPL>& s, uint8_t* out, StLds<CPL>* lds, uint64_t seed, uint32_t iter,
                           uint32_t member, uint32_t swarm)
 {
