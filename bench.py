@@ -135,9 +135,22 @@ def run_gpu(args, engine: str):
     stream = torch.cuda.Stream()
     P = sum(p["num_swarms"] * p["particles_per_swarm"] for _, _, p in insts)
 
+    plan = None
+
     def make():
+        nonlocal plan
         prms = [q.make_params(stream=stream.cuda_stream, engine=engine, **p) for _, _, p in insts]
-        return q.Swarm([(A, B) for A, B, _ in insts], prms)
+        h = q.Swarm([(A, B) for A, B, _ in insts], prms)
+        if not args.no_tune:
+            # the launch plan is chosen on the handle's own work and the handle
+            # returned to iteration 0: set-up, before the timed region
+            if plan is None:
+                plan = h.tune(32)
+            else:
+                h.set_plan(plan["stream_chains"], plan["split"], plan["iters_per_graph"])
+        else:
+            plan = h.plan()
+        return h
 
     sw = make()
     paths = sorted(set(sw.path(k)[0] for k in range(len(insts))))
@@ -203,7 +216,7 @@ def run_gpu(args, engine: str):
     roof["avg_ms"] = round(avg_ms, 4)  # per launch
     return dict(value=value, ms=secs * 1e3 / args.steps, path=path, sym=sym, P=P, n=n, roofline=roof,
                 stage_ms={k: round(v / max(iters, 1) / groups, 4) for k, v in stage_ms.items()},
-                groups=groups, instances=len(insts))
+                groups=groups, instances=len(insts), plan=plan)
 
 
 def cpu_baseline(target_s: float = 15.0, max_steps: int = 50, threads: int = 16, swarms: int | None = None):
@@ -275,6 +288,7 @@ def main():
                          "(64 instances, n 20..150); the CPU baseline runs with the headline only")
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan instead of the tuned one")
     ap.add_argument("--no-profile-pass", action="store_true",
                     help="skip the second, event-timed run (for kernel traces of the timed region alone)")
     ap.add_argument("--traffic-calibration", action="store_true",
@@ -329,6 +343,7 @@ def main():
         "roofline": res["roofline"],
         "stage_ms": res["stage_ms"],
         "stream_groups": res["groups"],
+        "plan": res["plan"],
     }
     if res["instances"] > 1:
         line["config"]["instances"] = res["instances"]

@@ -94,9 +94,10 @@ typedef struct {
  *    paper's GlobalMax) or QAP_SX_PICK_COLUMN (columns visited in a random
  *    order, each taking its largest key over the rows left; runs on the
  *    per-stage kernels, whatever the engine).
- *  stream_groups: 0 = automatic (independent swarms on the fused kernel are
- *    stepped as up to 3 concurrent groups of swarms, see qap_swarm_step), or 1-3
- *    to set the number of groups (results are the same for every choice). */
+ *  stream_groups: 0 = automatic (swarms on the fused kernel are stepped as up
+ *    to 3 concurrent groups of swarms, see qap_swarm_step and qap_plan), or
+ *    1-4 to set the number of groups of this instance (results are the same
+ *    for every choice). */
 typedef struct {
     int32_t num_swarms;
     int32_t particles_per_swarm;
@@ -178,6 +179,44 @@ int qap_swarm_init_batch(const qap_instance* insts, const qap_params* prms, int3
  * first call captures each group's iteration into a HIP graph, replayed once
  * per iteration; a stream that cannot be captured keeps eager launches. */
 int qap_swarm_step(qap_swarm* h, int32_t iterations);
+
+/* Launch plans and the autotuner (runtime; no passage of the paper: the
+ * paper launches separate kernels per iteration from its host, Sec. 3.3).
+ * A plan says how the iterations of a handle are launched; results are
+ * bit-identical under every plan.
+ *   stream_chains: concurrent chains of launches, each on its own stream
+ *     (1..QAP_MAX_CHAINS; the device has 4 hardware queues per process).
+ *   split: QAP_SPLIT_SWARMS -- every instance's swarms are spread over the
+ *     chains (an instance whose stream_groups parameter is set keeps that many
+ *     groups at most); QAP_SPLIT_INSTANCES -- whole instances, the heaviest
+ *     (particles x n^2) first onto the least loaded chain.
+ *   iters_per_graph: 0 = eager kernel launches; k >= 1 (at most 64) =
+ *     iterations replayed from graphs of k iterations (single-iteration graphs
+ *     for the rest of a step and around migrations).
+ *   ms_per_iteration: filled by qap_swarm_tune (the chosen plan's time).
+ * A handle starts on the plan cached for its workload (see qap_swarm_tune),
+ * else on 3 chains (or the instances' stream_groups), split by swarms, graphs
+ * of 8 iterations.  qap_swarm_set_plan may be called between any two steps
+ * (QAP_ERR_INVALID_ARG for a plan outside the ranges above).
+ * qap_swarm_tune times every plan (chains 1..4 x split x {eager, 1, 8}
+ * iterations per graph; the instance split only for several instances) on the
+ * handle's own work, each from iteration 0 -- 10 iterations of warm-up, then
+ * trial_iterations (1..4096) between events -- keeps the fastest, and returns
+ * the handle to iteration 0 (the state init made, re-created from the seed).  It must be called before the
+ * first step (QAP_ERR_INVALID_ARG otherwise).  If the environment variable
+ * QAP_SWARM_TUNE_CACHE names a file, the choice is appended to it under a
+ * signature of the device and the workload, and later handles with the same
+ * signature start on it without timing. */
+enum { QAP_MAX_CHAINS = 4, QAP_SPLIT_SWARMS = 0, QAP_SPLIT_INSTANCES = 1 };
+typedef struct {
+    int32_t stream_chains;
+    int32_t split;
+    int32_t iters_per_graph;
+    float ms_per_iteration;
+} qap_plan;
+int qap_swarm_get_plan(qap_swarm* h, qap_plan* plan);
+int qap_swarm_set_plan(qap_swarm* h, const qap_plan* plan);
+int qap_swarm_tune(qap_swarm* h, int32_t trial_iterations, qap_plan* chosen);
 
 /* Runtime introspection (no passage of the paper).
  * *active (may be NULL) = 1 if qap_swarm_step replays captured graphs (0:

@@ -32,7 +32,7 @@ EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swar
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
            "qap_swarm_deltas", "qap_swarm_path", "qap_swarm_graph", "qap_swarm_stats", "qap_swarm_profile",
            "qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_fail_alloc", "qap_swarm_live_allocations",
-           "qap_swarm_stats_noalloc"]
+           "qap_swarm_stats_noalloc", "qap_swarm_get_plan", "qap_swarm_set_plan", "qap_swarm_tune"]
 STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
@@ -48,6 +48,11 @@ class qap_params(ctypes.Structure):
                 ("local_search", ctypes.c_int32), ("delta_path", ctypes.c_int32), ("engine", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("stream", ctypes.c_void_p), ("stream_groups", ctypes.c_int32),
                 ("sx_procedure", ctypes.c_int32)]
+
+
+class qap_plan(ctypes.Structure):
+    _fields_ = [("stream_chains", ctypes.c_int32), ("split", ctypes.c_int32), ("iters_per_graph", ctypes.c_int32),
+                ("ms_per_iteration", ctypes.c_float)]
 
 
 class qap_state(ctypes.Structure):
@@ -93,6 +98,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                   P(ctypes.c_int64), P(ctypes.c_int64)]
     L.qap_swarm_stats_noalloc.argtypes = L.qap_swarm_stats.argtypes
+    L.qap_swarm_get_plan.argtypes = [vp, P(qap_plan)]
+    L.qap_swarm_set_plan.argtypes = [vp, P(qap_plan)]
+    L.qap_swarm_tune.argtypes = [vp, ctypes.c_int32, P(qap_plan)]
     L.qap_swarm_profile.argtypes = [vp, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_int64)]
     L.qap_swarm_destroy.argtypes = [vp]
     L.qap_swarm_destroy.restype = None
@@ -294,6 +302,23 @@ class Swarm:
         s = ctypes.c_int32()
         _check(load_library().qap_swarm_path(self.h, instance, ctypes.byref(p), ctypes.byref(s)), "qap_swarm_path")
         return {QAP_PATH_INT8_MFMA: "int8", QAP_PATH_INT32: "int32", QAP_PATH_SPLIT_MFMA: "split"}[p.value], bool(s.value)
+
+    def plan(self) -> dict:
+        """The launch plan: stream chains, split (0 swarms, 1 instances), iterations per graph (0 eager)."""
+        p = qap_plan()
+        _check(load_library().qap_swarm_get_plan(self.h, ctypes.byref(p)), "qap_swarm_get_plan")
+        return dict(stream_chains=p.stream_chains, split=p.split, iters_per_graph=p.iters_per_graph)
+
+    def set_plan(self, stream_chains: int, split: int = 0, iters_per_graph: int = 8) -> None:
+        p = qap_plan(int(stream_chains), int(split), int(iters_per_graph), 0.0)
+        _check(load_library().qap_swarm_set_plan(self.h, ctypes.byref(p)), "qap_swarm_set_plan")
+
+    def tune(self, trial_iterations: int = 16) -> dict:
+        """Time every launch plan on this handle's work, keep the fastest, return to iteration 0."""
+        p = qap_plan()
+        _check(load_library().qap_swarm_tune(self.h, int(trial_iterations), ctypes.byref(p)), "qap_swarm_tune")
+        return dict(stream_chains=p.stream_chains, split=p.split, iters_per_graph=p.iters_per_graph,
+                    ms_per_iteration=round(float(p.ms_per_iteration), 5))
 
     def graph_active(self) -> bool:
         """Whether stepping replays captured HIP graphs."""

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <cstdio>
 #include <mutex>
+#include <string>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -20,13 +22,19 @@ using qap::InstDesc;
 
 namespace {
 
-// Independent swarms of an instance on the fused kernel are stepped as up to
-// kStreamGroups groups of swarms, each on its own stream: the groups share
-// nothing within an iteration, so one group's end-of-iteration tail overlaps
-// another group's work (measured: 3 groups step the 10,000-particle n = 128
-// workload about 20 % faster than one launch chain).  More than 3 would
-// exceed the device's hardware queues per process (4).
+// Swarms on the fused kernel are stepped as concurrent chains of launches,
+// each on its own stream (the device has 4 hardware queues per process): one
+// chain's end-of-iteration tail overlaps another chain's work.  The default is
+// 3 chains, each holding a slice of every instance's swarms (measured: 3
+// chains step the 10,000-particle n = 128 workload about 20 % faster than one).
 constexpr int kStreamGroups = 3;
+constexpr int kMaxChains = QAP_MAX_CHAINS;
+
+// Iterations captured into one graph: consecutive launches of one graph run
+// back to back on the device, while each new graph launch on a stream starts
+// about 0.1 ms after the previous one ended (measured on the 64-instance
+// batch), so steps replay graphs of several iterations.
+constexpr int kItersPerGraph = 8;
 
 struct Instance {
     InstDesc d{};                 // the whole instance (iteration 0, state import/export, eval)
@@ -35,8 +43,10 @@ struct Instance {
     bool stepped = false;         // a step ran since init / set_state: the buffers of the previous state hold it
     long long t = 0;              // completed iterations (host copy of the device counter)
     int* order = nullptr;         // [m] migration ranking scratch
-    int groups = 1;               // stream groups stepping this instance
+    int groups = 1;               // swarm groups of the instance under the current plan
     std::vector<InstDesc> gdesc;  // [groups] descriptor of each group's swarms
+    std::vector<int> chain;       // [groups] launch chain (stream) of each group
+    int param_groups = 0;         // stream_groups of the instance's parameters (0: automatic)
     std::vector<void*> allocs;
 };
 
@@ -65,13 +75,23 @@ struct StepPlan {
 
 }  // namespace
 
+// A launch plan: how the iterations of a handle are spread over streams and
+// launched.  Results do not depend on it (states are bit-identical).
+struct PlanCfg {
+    int chains = kStreamGroups;  // concurrent launch chains, 1..kMaxChains
+    int split = 0;               // 0: every instance's swarms over the chains; 1: whole instances over the chains
+    int ipg = 8;                 // iterations per captured graph; 0: eager launches
+};
+
 struct qap_swarm {
     std::vector<Instance> inst;
+    PlanCfg cfg;
     StepPlan init;                        // whole instances: iteration 0
     std::vector<StepPlan> plans;          // one per stream group
     std::vector<hipStream_t> gstream;     // [groups]; gstream[0] = stream, the others owned
     std::vector<hipEvent_t> gevent;       // [groups]: fork (0) and joins (1..)
     std::vector<hipGraphExec_t> graphs;   // [groups] one iteration each, captured at the first step
+    std::vector<hipGraphExec_t> graphs_k; // [groups] cfg.ipg iterations each
     std::vector<int> migr;                // instances in migration mode stepped in several groups
     qap::InstDesc* migr_descs = nullptr;  // device [migr.size()]: their whole-instance descriptors
     hipStream_t stream = nullptr;
@@ -196,7 +216,7 @@ int check_params(const qap_instance* in, const qap_params* p)
     if (p->local_search < 0 || p->local_search > QAP_MAX_EXCHANGES) return QAP_ERR_INVALID_ARG;
     if (p->delta_path < QAP_PATH_AUTO || p->delta_path > QAP_PATH_SPLIT_MFMA) return QAP_ERR_INVALID_ARG;
     if (p->engine != QAP_ENGINE_FUSED && p->engine != QAP_ENGINE_PLAIN) return QAP_ERR_INVALID_ARG;
-    if (p->stream_groups < 0 || p->stream_groups > kStreamGroups) return QAP_ERR_INVALID_ARG;
+    if (p->stream_groups < 0 || p->stream_groups > kMaxChains) return QAP_ERR_INVALID_ARG;
     if (p->sx_procedure != QAP_SX_SECOND_TARGET && p->sx_procedure != QAP_SX_PICK_COLUMN) return QAP_ERR_INVALID_ARG;
     return QAP_OK;
 }
@@ -250,6 +270,8 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
     *split = pth == 3 ? spl : 0;
     return QAP_OK;
 }
+
+int init_state(qap_swarm* h, Instance& I);
 
 int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_params* p, int path, int sym,
                    int mul24, int zd, int split)
@@ -350,25 +372,48 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
     TRY(dalloc(I, &d.PG, (size_t)I.m * n));
     TRY(dalloc(I, &d.goalPG, (size_t)I.m));
     TRY(dalloc(I, &d.smin, (size_t)I.m));
-    I.groups = (h->engine == QAP_ENGINE_FUSED && qap::fused_supported(d))
-                   ? std::min(p->stream_groups > 0 ? p->stream_groups : kStreamGroups, I.m) : 1;
-    TRY(dalloc(I, &d.best, (size_t)I.groups));
-    TRY(dalloc(I, &d.iter, (size_t)I.groups));
+    I.param_groups = p->stream_groups;
+    TRY(dalloc(I, &d.best, (size_t)kMaxChains));
+    TRY(dalloc(I, &d.iter, (size_t)kMaxChains));
     TRY(dalloc(I, &I.order, (size_t)I.m));
     d.order = I.order;
     TRY(dalloc(I, &d.scratch, (size_t)h->grid_gd * nn * (sym ? 1 : 2)));
-    // iteration 0
+#undef TRY
+    return init_state(h, I);
+}
+
+// Iteration 0 of an instance on the handle's stream (the bests follow, batched
+// over the handle): no swarm best yet, empty best-ever records, counters at 0,
+// random permutations and velocities, their goals.
+int init_state(qap_swarm* h, Instance& I)
+{
+    const InstDesc& d = I.d;
     std::vector<long long> big((size_t)I.m, LLONG_MAX);
-    TRY(hipMemcpy(d.goalPG, big.data(), sizeof(long long) * I.m, hipMemcpyHostToDevice));
-    std::vector<qap::BestRec> none((size_t)I.groups);
+    hipError_t e = hipMemcpy(d.goalPG, big.data(), sizeof(long long) * I.m, hipMemcpyHostToDevice);
+    std::vector<qap::BestRec> none((size_t)kMaxChains);
     for (qap::BestRec& r : none) {
         std::memset(&r, 0, sizeof r);
         r.goal = LLONG_MAX;
     }
-    TRY(hipMemcpy(d.best, none.data(), sizeof(qap::BestRec) * I.groups, hipMemcpyHostToDevice));
-    const std::vector<int> zeros((size_t)I.groups, 0);
-    TRY(hipMemcpy(d.iter, zeros.data(), sizeof(int) * I.groups, hipMemcpyHostToDevice));
-    // group descriptors: swarms [g0, g0 + mj) seen as an instance of their own
+    if (e == hipSuccess) e = hipMemcpy(d.best, none.data(), sizeof(qap::BestRec) * kMaxChains, hipMemcpyHostToDevice);
+    const std::vector<int> zeros((size_t)kMaxChains, 0);
+    if (e == hipSuccess) e = hipMemcpy(d.iter, zeros.data(), sizeof(int) * kMaxChains, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = qap::launch_init(d, h->stream);
+    if (e == hipSuccess)
+        e = qap::launch_goal_delta_i32(d, I.mul24, h->grid_gd, d.X[0], I.P, 2, nullptr, nullptr, h->stream);
+    I.t = 0;
+    I.stepped = false;
+    return dev_err(nullptr, e);
+}
+
+// Group descriptors of an instance under a plan: swarms [g0, g0 + mj) of
+// group j seen as an instance of their own, with its own iteration counter
+// and best-ever record.
+void make_groups(Instance& I, int groups)
+{
+    const InstDesc& d = I.d;
+    const size_t n = (size_t)I.n, nn = n * n;
+    I.groups = groups;
     I.gdesc.clear();
     for (int j = 0, g0 = 0; j < I.groups; ++j) {
         const int mj = I.m / I.groups + (j < I.m % I.groups ? 1 : 0);
@@ -401,10 +446,6 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
         I.gdesc.push_back(gd);
         g0 += mj;
     }
-    TRY(qap::launch_init(d, h->stream));
-    TRY(qap::launch_goal_delta_i32(d, mul24, h->grid_gd, d.X[0], I.P, 2, nullptr, nullptr, h->stream));
-#undef TRY
-    return QAP_OK;
 }
 
 template <class T>
@@ -486,33 +527,110 @@ int build_plan(qap_swarm* h, StepPlan& pl, const std::vector<qap::InstDesc>& all
     return QAP_OK;
 }
 
-// The whole-instance plan (iteration 0) and one plan per stream group, with
-// the groups' streams and fork/join events.
-int build_plans(qap_swarm* h)
+// The best-ever record of an instance from its groups' records: the lowest
+// goal, first reached (earliest iteration, then lowest swarm) -- the record a
+// single chain over all swarms keeps.
+qap::BestRec combine_best(const std::vector<qap::BestRec>& r)
 {
+    qap::BestRec b = r[0];
+    for (size_t j = 1; j < r.size(); ++j)
+        if (r[j].goal < b.goal || (r[j].goal == b.goal && (r[j].iter < b.iter || (r[j].iter == b.iter && r[j].swarm < b.swarm))))
+            b = r[j];
+    return b;
+}
+
+// Quiesce a handle and release its launch plan: the chains' plans, graphs and
+// migration table (streams and events are kept for reuse).
+void drop_plan(qap_swarm* h)
+{
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    for (hipStream_t st : h->gstream) (void)hipStreamSynchronize(st);
+    for (hipGraphExec_t& g : h->graphs)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    for (hipGraphExec_t& g : h->graphs_k)
+        if (g) (void)hipGraphExecDestroy(g), g = nullptr;
+    for (StepPlan& pl : h->plans) free_plan(pl);
+    h->plans.clear();
+    dev_free(h->migr_descs);
+    h->migr_descs = nullptr;
+    h->migr.clear();
+    h->graph_failed = false;
+}
+
+// Algorithmic bytes of one iteration of an instance (its weight when whole
+// instances are spread over the chains).
+double instance_weight(const Instance& I)
+{
+    return (double)I.P * (8.0 * I.n * I.n + 3.0 * I.n + 24.0);
+}
+
+// Put a handle on launch plan c: each instance's swarm groups and their
+// chains, one step plan per chain, the streams and events of the chains.
+// The instances' per-group best records are first merged into record 0 and
+// every group counter set to the instance's iteration, so a plan can change
+// between any two steps.
+int apply_plan(qap_swarm* h, const PlanCfg& c)
+{
+    drop_plan(h);
     const int count = (int)h->inst.size();
-    std::vector<qap::InstDesc> whole;
-    std::vector<int> owner;
-    int groups = 1;
-    for (int k = 0; k < count; ++k) {
-        whole.push_back(h->inst[(size_t)k].d);
-        owner.push_back(k);
-        groups = std::max(groups, h->inst[(size_t)k].groups);
+    for (Instance& I : h->inst) {
+        std::vector<qap::BestRec> r((size_t)kMaxChains);
+        int t = 0;
+        hipError_t e = hipMemcpy(r.data(), I.d.best, sizeof(qap::BestRec) * kMaxChains, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&t, I.d.iter, sizeof t, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return dev_err(h, e);
+        r.resize((size_t)std::max(I.groups, 1));
+        std::vector<qap::BestRec> out((size_t)kMaxChains);
+        for (qap::BestRec& b : out) {
+            std::memset(&b, 0, sizeof b);
+            b.goal = LLONG_MAX;
+        }
+        out[0] = combine_best(r);
+        const std::vector<int> ts((size_t)kMaxChains, t);
+        e = hipMemcpy(I.d.best, out.data(), sizeof(qap::BestRec) * kMaxChains, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(I.d.iter, ts.data(), sizeof(int) * kMaxChains, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return dev_err(h, e);
     }
-    int rc = build_plan(h, h->init, whole, owner);
-    if (rc != QAP_OK) return rc;
-    h->plans.resize((size_t)groups);
-    for (int j = 0; j < groups; ++j) {
+    // groups and chains
+    std::vector<double> load((size_t)c.chains, 0.0);
+    std::vector<int> order((size_t)count);
+    for (int k = 0; k < count; ++k) order[(size_t)k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return instance_weight(h->inst[(size_t)a]) > instance_weight(h->inst[(size_t)b]);
+    });
+    for (int k : order) {
+        Instance& I = h->inst[(size_t)k];
+        const bool fused = h->engine == QAP_ENGINE_FUSED && qap::fused_supported(I.d);
+        if (c.split == 0) {
+            // an instance whose parameters fix its number of groups keeps it
+            const int cap = I.param_groups > 0 ? I.param_groups : c.chains;
+            make_groups(I, fused ? std::min({c.chains, I.m, cap}) : 1);
+            I.chain.assign((size_t)I.groups, 0);
+            for (int j = 0; j < I.groups; ++j) I.chain[(size_t)j] = j;
+        } else {
+            // whole instances, the heaviest first onto the least loaded chain
+            make_groups(I, 1);
+            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            I.chain.assign(1, q);
+            load[(size_t)q] += instance_weight(I);
+        }
+    }
+    int G = 1;
+    for (const Instance& I : h->inst)
+        for (int q : I.chain) G = std::max(G, q + 1);
+    h->plans.resize((size_t)G);
+    for (int q = 0; q < G; ++q) {
         std::vector<qap::InstDesc> descs;
         std::vector<int> own;
         for (int k = 0; k < count; ++k) {
             const Instance& I = h->inst[(size_t)k];
-            if (j < I.groups) {
-                descs.push_back(I.gdesc[(size_t)j]);
-                own.push_back(k);
-            }
+            for (int j = 0; j < I.groups; ++j)
+                if (I.chain[(size_t)j] == q) {
+                    descs.push_back(I.gdesc[(size_t)j]);
+                    own.push_back(k);
+                }
         }
-        rc = build_plan(h, h->plans[(size_t)j], descs, own);
+        const int rc = build_plan(h, h->plans[(size_t)q], descs, own);
         if (rc != QAP_OK) return rc;
     }
     std::vector<qap::InstDesc> mig;
@@ -524,34 +642,108 @@ int build_plans(qap_swarm* h)
         }
     }
     if (!mig.empty()) {
-        const hipError_t e = plan_upload(h->init, &h->migr_descs, mig);
+        void* q = nullptr;
+        hipError_t e = dev_malloc(&q, sizeof(qap::InstDesc) * mig.size());
+        if (e == hipSuccess) e = hipMemcpy(q, mig.data(), sizeof(qap::InstDesc) * mig.size(), hipMemcpyHostToDevice);
+        h->migr_descs = static_cast<qap::InstDesc*>(q);
         if (e != hipSuccess) return dev_err(nullptr, e);
     }
-    h->gstream.assign(1, h->stream);
-    h->graphs.assign((size_t)groups, nullptr);
-    for (int j = 0; j < groups; ++j) {
+    if (h->gstream.empty()) h->gstream.push_back(h->stream);
+    while ((int)h->gstream.size() < G) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return QAP_ERR_DEVICE;
+        h->gstream.push_back(st);
+    }
+    while ((int)h->gevent.size() < G) {
         hipEvent_t ev;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return QAP_ERR_DEVICE;
         h->gevent.push_back(ev);
-        if (j > 0) {
-            hipStream_t st;
-            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return QAP_ERR_DEVICE;
-            h->gstream.push_back(st);
-        }
     }
+    h->graphs.assign((size_t)G, nullptr);
+    h->graphs_k.assign((size_t)G, nullptr);
+    h->cfg = c;
     return QAP_OK;
 }
 
-// The best-ever record of an instance from its groups' records: the lowest
-// goal, first reached (earliest iteration, then lowest swarm) -- the record a
-// single chain over all swarms keeps.
-qap::BestRec combine_best(const std::vector<qap::BestRec>& r)
+// The plan a handle starts with: as many chains as the instances' parameters
+// ask for (3 when automatic), swarms split over them, graphs of 8 iterations.
+PlanCfg default_plan(const qap_swarm* h)
 {
-    qap::BestRec b = r[0];
-    for (size_t j = 1; j < r.size(); ++j)
-        if (r[j].goal < b.goal || (r[j].goal == b.goal && (r[j].iter < b.iter || (r[j].iter == b.iter && r[j].swarm < b.swarm))))
-            b = r[j];
-    return b;
+    PlanCfg c;
+    c.chains = 1;
+    for (const Instance& I : h->inst) c.chains = std::max(c.chains, I.param_groups > 0 ? I.param_groups : kStreamGroups);
+    c.split = 0;
+    c.ipg = kItersPerGraph;
+    return c;
+}
+
+// ------------------------------------------------------------------ plan cache
+// The plans chosen by qap_swarm_tune are kept in a text file named by the
+// environment variable QAP_SWARM_TUNE_CACHE, one line per workload signature:
+//   <signature> <chains> <split> <iterations per graph> <ms per iteration>
+// The signature hashes (FNV-1a, 64 bits) the device's architecture name and
+// compute-unit count and, per instance, what the launches depend on: n, the
+// swarm layout, the contraction path and kind, the mode and the engine.
+std::string plan_signature(const qap_swarm* h)
+{
+    hipDeviceProp_t prop{};
+    (void)hipGetDeviceProperties(&prop, h->device);
+    std::string key = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "/" +
+                      std::to_string(h->engine);
+    for (const Instance& I : h->inst) {
+        const InstDesc& d = I.d;
+        key += ";" + std::to_string(d.n) + "," + std::to_string(d.m) + "," + std::to_string(d.S) + "," +
+               std::to_string(d.path) + "," + std::to_string(d.split) + "," + std::to_string(d.sym) + "," +
+               std::to_string(d.zd) + "," + std::to_string(d.sx) + "," + std::to_string(d.ls) + "," +
+               std::to_string(d.migrate ? d.period : 0) + "," + std::to_string(I.param_groups);
+    }
+    unsigned long long x = 1469598103934665603ull;
+    for (unsigned char ch : key) {
+        x ^= ch;
+        x *= 1099511628211ull;
+    }
+    char buf[17];
+    std::snprintf(buf, sizeof buf, "%016llx", x);
+    return std::string(buf);
+}
+
+const char* cache_path() { return std::getenv("QAP_SWARM_TUNE_CACHE"); }
+
+bool valid_plan(const PlanCfg& c)
+{
+    return c.chains >= 1 && c.chains <= kMaxChains && (c.split == 0 || c.split == 1) && c.ipg >= 0 &&
+           c.ipg <= 64;
+}
+
+// The cached plan of this handle's signature, if the cache names one.
+bool cached_plan(const qap_swarm* h, PlanCfg* out)
+{
+    const char* path = cache_path();
+    if (!path || !*path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string sig = plan_signature(h);
+    char key[64];
+    PlanCfg c;
+    float ms = 0.0f;
+    bool found = false;
+    while (std::fscanf(f, "%63s %d %d %d %f", key, &c.chains, &c.split, &c.ipg, &ms) == 5)
+        if (sig == key && valid_plan(c)) {
+            *out = c;  // the last line for a signature wins
+            found = true;
+        }
+    std::fclose(f);
+    return found;
+}
+
+void store_plan(const qap_swarm* h, const PlanCfg& c, float ms)
+{
+    const char* path = cache_path();
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %.5f\n", plan_signature(h).c_str(), c.chains, c.split, c.ipg, ms);
+    std::fclose(f);
 }
 
 constexpr int kEvPerIter = 2 * QAP_NUM_STAGES;
@@ -650,10 +842,10 @@ int enqueue_iteration(qap_swarm* h, int j)
     return QAP_OK;
 }
 
-// Capture one iteration of group j into a graph (replayed once per
-// iteration).  A stream that cannot be captured leaves the handle on eager
-// launches.
-void capture_iteration(qap_swarm* h, int j)
+// Capture `iters` iterations of group j into a graph (replayed once per
+// `iters` iterations).  A stream that cannot be captured leaves the handle on
+// eager launches.
+void capture_iterations(qap_swarm* h, int j, int iters, hipGraphExec_t* out)
 {
     hipStream_t st = h->gstream[(size_t)j];
     hipGraph_t g = nullptr;
@@ -662,7 +854,8 @@ void capture_iteration(qap_swarm* h, int j)
         h->graph_failed = true;
         return;
     }
-    const int rc = enqueue_iteration(h, j);
+    int rc = QAP_OK;
+    for (int i = 0; i < iters && rc == QAP_OK; ++i) rc = enqueue_iteration(h, j);
     const hipError_t e = hipStreamEndCapture(st, &g);
     if (rc != QAP_OK || e != hipSuccess || !g) {
         if (g) (void)hipGraphDestroy(g);
@@ -671,12 +864,24 @@ void capture_iteration(qap_swarm* h, int j)
         h->graph_failed = true;
         return;
     }
-    if (hipGraphInstantiate(&h->graphs[(size_t)j], g, nullptr, nullptr, 0) != hipSuccess) {
+    if (hipGraphInstantiate(out, g, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGetLastError();
-        h->graphs[(size_t)j] = nullptr;
+        *out = nullptr;
         h->graph_failed = true;
     }
     (void)hipGraphDestroy(g);
+}
+
+// Whether Alg. 2 of an instance stepped in several groups falls due after
+// any of the iterations it + 1 .. it + count of this step call.
+bool migration_due(const qap_swarm* h, int it, int count)
+{
+    for (int k : h->migr) {
+        const Instance& I = h->inst[(size_t)k];
+        for (int c = 1; c <= count; ++c)
+            if ((I.t + it + c) % I.d.period == 0) return true;
+    }
+    return false;
 }
 
 int get_instance(qap_swarm* h, int32_t k, Instance** out)
@@ -712,11 +917,14 @@ void qap_swarm_destroy(qap_swarm* h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     for (hipGraphExec_t g : h->graphs)
         if (g) (void)hipGraphExecDestroy(g);
+    for (hipGraphExec_t g : h->graphs_k)
+        if (g) (void)hipGraphExecDestroy(g);
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : h->gevent) (void)hipEventDestroy(e);
     for (size_t j = 1; j < h->gstream.size(); ++j) (void)hipStreamDestroy(h->gstream[j]);
     free_plan(h->init);
     for (StepPlan& pl : h->plans) free_plan(pl);
+    dev_free(h->migr_descs);
     for (Instance& I : h->inst) free_instance(I);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     delete h;
@@ -772,7 +980,19 @@ int impl_init_batch(const qap_instance* insts, const qap_params* prms, int32_t c
                                       mul24[(size_t)k], zd[(size_t)k], split[(size_t)k]);
         if (rc != QAP_OK) return fail(rc);
     }
-    int rc = build_plans(h);
+    // the whole-instance plan (iteration 0), then the launch plan
+    std::vector<qap::InstDesc> whole;
+    std::vector<int> owner;
+    for (int k = 0; k < count; ++k) {
+        whole.push_back(h->inst[(size_t)k].d);
+        owner.push_back(k);
+    }
+    int rc = build_plan(h, h->init, whole, owner);
+    if (rc == QAP_OK) {
+        PlanCfg c = default_plan(h);
+        (void)cached_plan(h, &c);
+        rc = apply_plan(h, c);
+    }
     if (rc == QAP_OK) {
         hipError_t e = qap::launch_bests(h->init.descs, h->init.smap, h->init.total_swarms, count, 1, h->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
@@ -797,27 +1017,30 @@ int impl_step(qap_swarm* h, int32_t iterations)
         for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
         if (e != hipSuccess) return dev_err(h, e);
     }
-    for (int it = 0; it < iterations; ++it) {
+    for (int it = 0; it < iterations;) {
+        // a graph of several iterations where no migration join falls inside it
+        const int K = h->cfg.ipg;
+        const bool graphs = !h->profiling && K > 0 && !h->graph_failed;
+        const bool multi = graphs && K > 1 && iterations - it >= K && !migration_due(h, it, K);
+        const int chunk = multi ? K : 1;
         for (int j = 0; j < G; ++j) {
-            if (!h->profiling && !h->graphs[(size_t)j] && !h->graph_failed) capture_iteration(h, j);
-            if (!h->profiling && h->graphs[(size_t)j]) {
-                e = hipGraphLaunch(h->graphs[(size_t)j], h->gstream[(size_t)j]);
+            hipGraphExec_t* gx = multi ? &h->graphs_k[(size_t)j] : &h->graphs[(size_t)j];
+            if (graphs && !*gx) capture_iterations(h, j, chunk, gx);
+            if (graphs && *gx) {
+                e = hipGraphLaunch(*gx, h->gstream[(size_t)j]);
                 if (e != hipSuccess) return dev_err(h, e);
                 continue;
             }
-            const int rc = enqueue_iteration(h, j);
-            if (rc != QAP_OK) return rc;
+            for (int c = 0; c < chunk; ++c) {
+                const int rc = enqueue_iteration(h, j);
+                if (rc != QAP_OK) return rc;
+            }
         }
-        if (h->profiling) h->prof_iters += 1;
-        // Alg. 2 of the instances stepped in several groups, when due: the
-        // groups join, one launch migrates, and they fork again before the
-        // next iteration reads P^G
-        bool due = false;
-        for (int k : h->migr) {
-            const Instance& I = h->inst[(size_t)k];
-            due = due || (I.t + it + 1) % I.d.period == 0;
-        }
-        if (due) {
+        if (h->profiling) h->prof_iters += chunk;
+        // Alg. 2 of the instances stepped in several groups, when due (only
+        // after single iterations): the groups join, one launch migrates, and
+        // they fork again before the next iteration reads P^G
+        if (!multi && migration_due(h, it, 1)) {
             for (int j = 1; j < G && e == hipSuccess; ++j) {
                 e = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
                 if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
@@ -827,6 +1050,7 @@ int impl_step(qap_swarm* h, int32_t iterations)
             for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
             if (e != hipSuccess) return dev_err(h, e);
         }
+        it += chunk;
     }
     for (Instance& I : h->inst) {
         I.stepped = true;
@@ -979,7 +1203,7 @@ int impl_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
     if (e == hipSuccess) e = perms_in(st->PG, m, d.PG);
     if (e == hipSuccess) e = hipMemcpy(d.goalPG, st->goalPG, m * 8, hipMemcpyHostToDevice);
     // the record goes to group 0, the other groups' records start empty
-    std::vector<qap::BestRec> recs((size_t)I->groups);
+    std::vector<qap::BestRec> recs((size_t)kMaxChains);
     for (qap::BestRec& r : recs) {
         std::memset(&r, 0, sizeof r);
         r.goal = LLONG_MAX;
@@ -989,9 +1213,9 @@ int impl_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
     recs[0].swarm = st->best_swarm;
     recs[0].member = st->best_particle;
     for (size_t j = 0; j < n; ++j) recs[0].perm[j] = (uint8_t)st->best_perm[j];
-    const std::vector<int> ts((size_t)I->groups, t);
-    if (e == hipSuccess) e = hipMemcpy(d.best, recs.data(), sizeof(qap::BestRec) * I->groups, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d.iter, ts.data(), sizeof(int) * I->groups, hipMemcpyHostToDevice);
+    const std::vector<int> ts((size_t)kMaxChains, t);
+    if (e == hipSuccess) e = hipMemcpy(d.best, recs.data(), sizeof(qap::BestRec) * kMaxChains, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d.iter, ts.data(), sizeof(int) * kMaxChains, hipMemcpyHostToDevice);
     I->stepped = false;  // the previous-state buffers no longer belong to this state
     I->t = t;
     return dev_err(h, e);
@@ -1227,10 +1451,116 @@ int impl_stats_noalloc(qap_swarm* h, int32_t instance, int32_t nq, const int32_t
 int impl_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
-    bool all = !h->graphs.empty();
+    bool all = !h->graphs.empty() && h->cfg.ipg > 0 && !h->graph_failed;
     for (hipGraphExec_t g : h->graphs) all = all && g != nullptr;
     if (active) *active = (all && !h->profiling) ? 1 : 0;
     if (streams) *streams = (int32_t)h->plans.size();
+    return QAP_OK;
+}
+
+int impl_get_plan(qap_swarm* h, qap_plan* plan)
+{
+    if (!h || !plan) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    plan->stream_chains = h->cfg.chains;
+    plan->split = h->cfg.split;
+    plan->iters_per_graph = h->cfg.ipg;
+    plan->ms_per_iteration = 0.0f;
+    return QAP_OK;
+}
+
+int impl_set_plan(qap_swarm* h, const qap_plan* plan)
+{
+    if (!h || !plan) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    PlanCfg c;
+    c.chains = plan->stream_chains;
+    c.split = plan->split;
+    c.ipg = plan->iters_per_graph;
+    if (!valid_plan(c)) return QAP_ERR_INVALID_ARG;
+    return apply_plan(h, c);
+}
+
+// The state init made, re-created from the seed (every instance at
+// iteration 0, then the initial bests); waits.
+int reset_state(qap_swarm* h)
+{
+    int rc = QAP_OK;
+    for (Instance& I : h->inst)
+        if (rc == QAP_OK) rc = init_state(h, I);
+    if (rc != QAP_OK) return rc;
+    hipError_t e = qap::launch_bests(h->init.descs, h->init.smap, h->init.total_swarms, (int)h->inst.size(), 1,
+                                     h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return dev_err(h, e);
+}
+
+constexpr int kTuneWarmup = 10;
+
+// Time every candidate plan on the handle's own work (from iteration 0, a
+// warm-up, then `trial` iterations between events on the handle's stream),
+// keep the fastest, and put the handle back to iteration 0 (the
+// initialisation is a function of the seed, so the state is exactly the one
+// init made).
+int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
+{
+    if (!h || trial < 1 || trial > 4096) return QAP_ERR_INVALID_ARG;
+    if (h->sticky != QAP_OK) return h->sticky;
+    if (h->profiling) return QAP_ERR_INVALID_ARG;
+    for (const Instance& I : h->inst)
+        if (I.t != 0 || I.stepped) return QAP_ERR_INVALID_ARG;  // tuning starts from iteration 0
+    std::vector<PlanCfg> cands;
+    const bool several = h->inst.size() > 1;
+    for (int split = 0; split <= (several ? 1 : 0); ++split)
+        for (int chains = 1; chains <= kMaxChains; ++chains)
+            for (int ipg : {0, 1, kItersPerGraph}) {
+                PlanCfg c;
+                c.chains = chains;
+                c.split = split;
+                c.ipg = ipg;
+                cands.push_back(c);
+            }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return QAP_ERR_DEVICE;
+    }
+    PlanCfg best = h->cfg;
+    float best_ms = 0.0f;
+    int rc = QAP_OK;
+    for (const PlanCfg& c : cands) {
+        // every plan is timed on the same iterations: from iteration 0, the
+        // first kTuneWarmup untimed (graph capture, the fast first iterations)
+        rc = apply_plan(h, c);
+        if (rc == QAP_OK) rc = reset_state(h);
+        if (rc != QAP_OK) break;
+        rc = impl_step(h, kTuneWarmup);
+        hipError_t e = rc == QAP_OK ? hipEventRecord(e0, h->stream) : hipSuccess;
+        if (rc == QAP_OK && e == hipSuccess) rc = impl_step(h, trial);
+        if (rc == QAP_OK && e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (rc == QAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (rc == QAP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rc == QAP_OK && e != hipSuccess) rc = dev_err(h, e);
+        if (rc != QAP_OK) break;
+        ms /= (float)trial;
+        if (best_ms == 0.0f || ms < best_ms) {
+            best = c;
+            best_ms = ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == QAP_OK) rc = apply_plan(h, best);
+    if (rc == QAP_OK) rc = reset_state(h);  // back to iteration 0
+    if (rc != QAP_OK) return rc;
+    store_plan(h, best, best_ms);
+    if (chosen) {
+        chosen->stream_chains = best.chains;
+        chosen->split = best.split;
+        chosen->iters_per_graph = best.ipg;
+        chosen->ms_per_iteration = best_ms;
+    }
     return QAP_OK;
 }
 
@@ -1407,6 +1737,37 @@ int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     try {
         return impl_graph(h, active, streams);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_get_plan(qap_swarm* h, qap_plan* plan)
+{
+    try {
+        return impl_get_plan(h, plan);
+    } catch (...) {
+        return QAP_ERR_NOMEM;
+    }
+}
+
+int qap_swarm_set_plan(qap_swarm* h, const qap_plan* plan)
+{
+    try {
+        return impl_set_plan(h, plan);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_tune(qap_swarm* h, int32_t trial_iterations, qap_plan* chosen)
+{
+    try {
+        return impl_tune(h, trial_iterations, chosen);
     } catch (const std::bad_alloc&) {
         return QAP_ERR_NOMEM;
     } catch (...) {

@@ -92,6 +92,11 @@ def test_graph_replays_equal_eager(q, engine):
     b.step(5)
     for k in range(len(cases)):
         assert_same(a.get_state(k), b.get_state(k), ("replays 7-11, instance", k))
+    # longer steps replay graphs of several iterations (and single ones for the rest)
+    a.step(19)
+    b.step(19)
+    for k in range(len(cases)):
+        assert_same(a.get_state(k), b.get_state(k), ("replays 12-30, instance", k))
     # a state written between replays is picked up by the next replay
     st = b.get_state(0)
     a.set_state(st, 0)
@@ -108,11 +113,12 @@ def test_stream_groups_bit_identical(q, migration):
     """Swarms stepped as 1, 2 or 3 concurrent stream groups give identical
     states: the groups only partition the swarms.  In migration mode the
     groups join at every iteration where Alg. 2 is due and one launch ranks
-    all swarms of the instance (period 3 here: several migrations in the run,
-    and steps that end on, before and after one)."""
+    all swarms of the instance (period 10 here: several migrations in the run,
+    steps that end on, before and after one); a final long step replays
+    graphs of several iterations between the migrations."""
     F, D = gen.uniform_instance(64, 0, 99, 31)
     cfg = run_cfg(num_swarms=7, particles_per_swarm=9, seed=17, migration=migration,
-                  migration_factor=0.3 if migration else 0.0, migration_period=3 if migration else 1)
+                  migration_factor=0.3 if migration else 0.0, migration_period=10 if migration else 1)
     announce("stream groups", migration)
     hs = [q.Swarm.create(F, D, engine="fused", stream_groups=g, **cfg) for g in (1, 2, 3)]
     assert [h.stream_groups() for h in hs] == [1, 2, 3]
@@ -129,5 +135,11 @@ def test_stream_groups_bit_identical(q, migration):
         moved += int((ref["goalPG"] != np.minimum(before["goalPG"], best_now)).sum())
     if migration:
         assert moved > 0  # Alg. 2 moved solutions within the run
+    for h in hs:
+        h.step(31)
+    ref = hs[0].get_state()
+    assert ref["t"] == 46
+    for h in hs[1:]:
+        assert_same(h.get_state(), ref, ("groups", h.stream_groups(), "after a long step"))
     for h in hs:
         h.close()
