@@ -189,7 +189,10 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  *   split: QAP_SPLIT_SWARMS -- every instance's swarms are spread over the
  *     chains (an instance whose stream_groups parameter is set keeps that many
  *     groups at most); QAP_SPLIT_INSTANCES -- whole instances, the heaviest
- *     (particles x n^2) first onto the least loaded chain.
+ *     (particles x n^2) first onto the least loaded chain; QAP_SPLIT_CLASSES --
+ *     whole kernel classes (instances sharing a launch: padded size,
+ *     contraction kind, symmetry and diagonals; the instances on per-stage
+ *     kernels form one more), the heaviest first onto the least loaded chain.
  *   iters_per_graph: 0 = eager kernel launches; k >= 1 (at most 64) =
  *     iterations replayed from graphs of k iterations (single-iteration graphs
  *     for the rest of a step and around migrations).
@@ -199,7 +202,8 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  * of 8 iterations.  qap_swarm_set_plan may be called between any two steps
  * (QAP_ERR_INVALID_ARG for a plan outside the ranges above).
  * qap_swarm_tune times every plan (chains 1..4 x split x {eager, 1, 8}
- * iterations per graph; the instance split only for several instances) on the
+ * iterations per graph; the instance and class splits only for several
+ * instances) on the
  * handle's own work, each from iteration 0 -- 10 iterations of warm-up, then
  * trial_iterations (1..4096) between events -- keeps the fastest, and returns
  * the handle to iteration 0 (the state init made, re-created from the seed).  It must be called before the
@@ -207,7 +211,7 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  * QAP_SWARM_TUNE_CACHE names a file, the choice is appended to it under a
  * signature of the device and the workload, and later handles with the same
  * signature start on it without timing. */
-enum { QAP_MAX_CHAINS = 4, QAP_SPLIT_SWARMS = 0, QAP_SPLIT_INSTANCES = 1 };
+enum { QAP_MAX_CHAINS = 4, QAP_SPLIT_SWARMS = 0, QAP_SPLIT_INSTANCES = 1, QAP_SPLIT_CLASSES = 2 };
 typedef struct {
     int32_t stream_chains;
     int32_t split;

@@ -45,8 +45,21 @@ hipError_t launch_migrate(const InstDesc* descs, int count, hipStream_t st);
 hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st);
 
-// Particles per workgroup of the fused kernel.
-constexpr int kFusedParticlesPerBlock = 4;
+// Particles (waves) per workgroup of a fused-kernel class.  The waves of a
+// workgroup share one LDS copy of F and D.  Larger workgroups where LDS, not
+// registers, limited the kernel: the npad-160 int8 symmetric kernels (F, D and
+// the per-wave data take 59 KB per 4-wave workgroup: 2 per CU, while the
+// registers allow 3 waves per SIMD) take 12 waves, as does the byte-split
+// npad-128 kernel with zero diagonals (four planes, 79 KB per 4-wave
+// workgroup); the byte-split npad-160 kernels (116 KB: one 4-wave workgroup
+// per CU) take 8, which they hold without spilling.  4 elsewhere.
+constexpr int fused_wpb(int npad, int wide, bool sym, bool zd)
+{
+    return (wide == 0 && sym && npad == 160) || (wide == 1 && npad == 128 && zd) ? 12
+           : (wide == 1 && npad == 160)                                          ? 8
+                                                                                   : 4;
+}
+int fused_particles_per_block(int npad, int wide, bool sym, bool zd);
 
 // Whether the fused kernel covers an instance (int8 path, or the byte-split
 // path with F and D symmetric; n <= 160; SecondTarget).

@@ -30,7 +30,7 @@ typedef int v16i __attribute__((ext_vector_type(16)));
 
 namespace {
 
-constexpr int kWaves = 4;  // particles (waves) per workgroup
+constexpr int kWaves = 4;  // particles (waves) per workgroup of the evaluation kernels
 
 __device__ __forceinline__ void wave_sync()
 {
@@ -572,13 +572,14 @@ __device__ __forceinline__ void write_particle(const InstDesc& d, int k, int cur
 template <int NP>
 constexpr int cols_per_lane() { return NP <= 64 ? 1 : NP <= 128 ? 2 : 4; }
 
-// TABLE: workgroup b steps particles blkmap[b].y .. +3 of instance
-// descs[blkmap[b].x] (its pointers marked global where they are used, see
-// gl); otherwise
-// workgroup b steps particles 4b .. 4b+3 of the instance passed as `one` (a
-// kernel argument, whose pointers the compiler knows to be global).
-// One workgroup of k_fused_step: particles first .. first + 3 of d.
-template <int NP, bool SYM, bool ZD>
+// WPB particles (waves) per workgroup, sharing one LDS copy of F and D (see
+// fused_wpb).  TABLE: workgroup b steps particles blkmap[b].y ..
+// + WPB - 1 of instance descs[blkmap[b].x] (its pointers marked global where
+// they are used, see gl); otherwise workgroup b steps particles WPB b .. of
+// the instance passed as `one` (a kernel argument, whose pointers the
+// compiler knows to be global).
+// One workgroup of k_fused_step: particles first .. first + WPB - 1 of d.
+template <int NP, bool SYM, bool ZD, int WPB>
 __device__ __forceinline__ void fused_step_block(const InstDesc& d, int first)
 {
     constexpr int CPL = cols_per_lane<NP>();  // column slots per lane
@@ -586,13 +587,13 @@ __device__ __forceinline__ void fused_step_block(const InstDesc& d, int first)
     __shared__ __attribute__((aligned(16))) int8_t sD[NP * lds_stride_d<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sFT[SYM ? 16 : NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) int8_t sDT[SYM ? 16 : NP * lds_stride_d<NP>()];
-    __shared__ __attribute__((aligned(16))) uint8_t sp[kWaves][NP];
+    __shared__ __attribute__((aligned(16))) uint8_t sp[WPB][NP];
     // per wave: the selection scratch of stage B, then the row info of stage C
     union WaveScratch {
         StLds<CPL> st;
         RowInfo ri[NP];
     };
-    __shared__ WaveScratch sws[kWaves];
+    __shared__ WaveScratch sws[WPB];
     load_instance_lds<NP, SYM>(d, sF, sD, sFT, sDT);
     __syncthreads();
 
@@ -610,15 +611,16 @@ __device__ __forceinline__ void fused_step_block(const InstDesc& d, int first)
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
-template <int NP, bool SYM, bool ZD, bool TABLE>
-__global__ __launch_bounds__(256) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
-                                                    const int2* __restrict__ blkmap)
+template <int NP, bool SYM, bool ZD, bool TABLE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
+                                                         const int2* __restrict__ blkmap)
 {
     if constexpr (TABLE) {
         const int2 bm = blkmap[blockIdx.x];
-        fused_step_block<NP, SYM, ZD>(descs[__builtin_amdgcn_readfirstlane(bm.x)], __builtin_amdgcn_readfirstlane(bm.y));
+        fused_step_block<NP, SYM, ZD, WPB>(descs[__builtin_amdgcn_readfirstlane(bm.x)],
+                                           __builtin_amdgcn_readfirstlane(bm.y));
     } else {
-        fused_step_block<NP, SYM, ZD>(one, (int)blockIdx.x * kWaves);
+        fused_step_block<NP, SYM, ZD, WPB>(one, (int)blockIdx.x * WPB);
     }
 }
 
@@ -838,12 +840,12 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
     bestkey = wave_min_i64(bestkey);
 }
 
-template <int NP, bool ZD, bool HS>
+template <int NP, bool ZD, bool HS, int WPB>
 __device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
 {
     constexpr int CPL = cols_per_lane<NP>();
     __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
-    __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[kWaves];
+    __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[WPB];
     load_wide_lds<NP>(d, spl);
     __syncthreads();
 
@@ -861,15 +863,16 @@ __device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
-template <int NP, bool ZD, bool HS, bool TABLE>
-__global__ __launch_bounds__(256) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
-                                                    const int2* __restrict__ blkmap)
+template <int NP, bool ZD, bool HS, bool TABLE, int WPB>
+__global__ __launch_bounds__(64 * WPB) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
+                                                         const int2* __restrict__ blkmap)
 {
     if constexpr (TABLE) {
         const int2 bm = blkmap[blockIdx.x];
-        fused_wide_block<NP, ZD, HS>(descs[__builtin_amdgcn_readfirstlane(bm.x)], __builtin_amdgcn_readfirstlane(bm.y));
+        fused_wide_block<NP, ZD, HS, WPB>(descs[__builtin_amdgcn_readfirstlane(bm.x)],
+                                          __builtin_amdgcn_readfirstlane(bm.y));
     } else {
-        fused_wide_block<NP, ZD, HS>(one, (int)blockIdx.x * kWaves);
+        fused_wide_block<NP, ZD, HS, WPB>(one, (int)blockIdx.x * WPB);
     }
 }
 
@@ -934,19 +937,21 @@ template <int NP, int WIDE, bool SYM, bool ZD>
 static hipError_t fused_launch_one(const InstDesc* one, const InstDesc* descs, const int2* blkmap, int blocks,
                                    hipStream_t st)
 {
-    const dim3 grid((unsigned)blocks), block(kWaves * kWave);
+    constexpr int WPB = fused_wpb(NP, WIDE, SYM, ZD);
+    const dim3 grid((unsigned)blocks), block(WPB * kWave);
     if constexpr (WIDE == 2 && NP > 128) {
         return hipErrorNotSupported;
     } else if constexpr (WIDE != 0) {
         if (one)
-            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, false>), grid, block, 0, st, *one, descs, blkmap);
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, false, WPB>), grid, block, 0, st, *one, descs, blkmap);
         else
-            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, true, WPB>), grid, block, 0, st, InstDesc{}, descs,
+                               blkmap);
     } else {
         if (one)
-            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, false>), grid, block, 0, st, *one, descs, blkmap);
+            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, false, WPB>), grid, block, 0, st, *one, descs, blkmap);
         else
-            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, true>), grid, block, 0, st, InstDesc{}, descs, blkmap);
+            hipLaunchKernelGGL((k_fused_step<NP, SYM, ZD, true, WPB>), grid, block, 0, st, InstDesc{}, descs, blkmap);
     }
     return hipGetLastError();
 }
@@ -967,6 +972,8 @@ static hipError_t fused_launch_np(int npad, const InstDesc* one, const InstDesc*
 
 bool split_supported(int npad, int split) { return npad <= 160 && (split != 3 || npad <= 128); }
 
+int fused_particles_per_block(int npad, int wide, bool sym, bool zd) { return fused_wpb(npad, wide, sym, zd); }
+
 bool fused_supported(const InstDesc& d)
 {
     return (d.path == 1 || (d.path == 3 && d.sym && split_supported(d.npad, d.split))) && d.npad <= 160 && d.sx == 0;
@@ -975,7 +982,6 @@ bool fused_supported(const InstDesc& d)
 hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st)
 {
-    static_assert(kWaves == kFusedParticlesPerBlock, "one wave per particle");
     if (blocks <= 0) return hipSuccess;
     if (wide == 1)
         return !sym ? hipErrorNotSupported

@@ -79,7 +79,7 @@ struct StepPlan {
 // launched.  Results do not depend on it (states are bit-identical).
 struct PlanCfg {
     int chains = kStreamGroups;  // concurrent launch chains, 1..kMaxChains
-    int split = 0;               // 0: every instance's swarms over the chains; 1: whole instances over the chains
+    int split = 0;               // 0: every instance's swarms over the chains; 1: whole instances; 2: whole classes
     int ipg = 8;                 // iterations per captured graph; 0: eager launches
 };
 
@@ -510,11 +510,11 @@ int build_plan(qap_swarm* h, StepPlan& pl, const std::vector<qap::InstDesc>& all
         FusedClass& fc = pl.fused[c];
         std::vector<qap::InstDesc> descs;
         std::vector<int2> blkmap;
+        const int wpb = qap::fused_particles_per_block(fc.npad, fc.wide, fc.sym, fc.zd);
         for (int k : members[c]) {
             const int j = (int)descs.size();
             descs.push_back(all[(size_t)k]);
-            for (int first = 0; first < all[(size_t)k].P; first += qap::kFusedParticlesPerBlock)
-                blkmap.push_back(make_int2(j, first));
+            for (int first = 0; first < all[(size_t)k].P; first += wpb) blkmap.push_back(make_int2(j, first));
         }
         fc.blocks = (int)blkmap.size();
         fc.host = descs;
@@ -607,13 +607,45 @@ int apply_plan(qap_swarm* h, const PlanCfg& c)
             make_groups(I, fused ? std::min({c.chains, I.m, cap}) : 1);
             I.chain.assign((size_t)I.groups, 0);
             for (int j = 0; j < I.groups; ++j) I.chain[(size_t)j] = j;
-        } else {
+        } else if (c.split == 1) {
             // whole instances, the heaviest first onto the least loaded chain
             make_groups(I, 1);
             const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
             I.chain.assign(1, q);
             load[(size_t)q] += instance_weight(I);
+        } else {
+            make_groups(I, 1);  // chains assigned per class below
         }
+    }
+    if (c.split == 2) {
+        // whole kernel classes (padded size, contraction kind, symmetry,
+        // diagonals; the per-stage instances form one more), the heaviest
+        // first onto the least loaded chain: each chain launches few classes
+        std::vector<long long> key((size_t)count);
+        for (int k = 0; k < count; ++k) {
+            const Instance& I = h->inst[(size_t)k];
+            const bool fused = h->engine == QAP_ENGINE_FUSED && qap::fused_supported(I.d);
+            key[(size_t)k] = fused ? ((long long)I.d.npad << 8) | (fused_kind(I.d) << 4) | (I.d.sym << 1) | I.d.zd : -1;
+        }
+        std::vector<long long> keys(key);
+        std::sort(keys.begin(), keys.end());
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        std::vector<double> weight(keys.size(), 0.0);
+        for (int k = 0; k < count; ++k)
+            weight[(size_t)(std::lower_bound(keys.begin(), keys.end(), key[(size_t)k]) - keys.begin())] +=
+                instance_weight(h->inst[(size_t)k]);
+        std::vector<int> cls(keys.size());
+        for (size_t i = 0; i < cls.size(); ++i) cls[i] = (int)i;
+        std::stable_sort(cls.begin(), cls.end(), [&](int a, int b) { return weight[(size_t)a] > weight[(size_t)b]; });
+        std::vector<int> chain_of(keys.size(), 0);
+        for (int ci : cls) {
+            const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            chain_of[(size_t)ci] = q;
+            load[(size_t)q] += weight[(size_t)ci];
+        }
+        for (int k = 0; k < count; ++k)
+            h->inst[(size_t)k].chain.assign(
+                1, chain_of[(size_t)(std::lower_bound(keys.begin(), keys.end(), key[(size_t)k]) - keys.begin())]);
     }
     int G = 1;
     for (const Instance& I : h->inst)
@@ -711,7 +743,7 @@ const char* cache_path() { return std::getenv("QAP_SWARM_TUNE_CACHE"); }
 
 bool valid_plan(const PlanCfg& c)
 {
-    return c.chains >= 1 && c.chains <= kMaxChains && (c.split == 0 || c.split == 1) && c.ipg >= 0 &&
+    return c.chains >= 1 && c.chains <= kMaxChains && c.split >= 0 && c.split <= 2 && c.ipg >= 0 &&
            c.ipg <= 64;
 }
 
@@ -1511,7 +1543,7 @@ int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
         if (I.t != 0 || I.stepped) return QAP_ERR_INVALID_ARG;  // tuning starts from iteration 0
     std::vector<PlanCfg> cands;
     const bool several = h->inst.size() > 1;
-    for (int split = 0; split <= (several ? 1 : 0); ++split)
+    for (int split = 0; split <= (several ? 2 : 0); ++split)
         for (int chains = 1; chains <= kMaxChains; ++chains)
             for (int ipg : {0, 1, kItersPerGraph}) {
                 PlanCfg c;

@@ -1,8 +1,9 @@
 """Launch plans and the autotuner.
 
-A plan (stream chains, swarms or whole instances over the chains, eager or
-graphs of k iterations) changes only how iterations are launched: states must
-be bit-identical under every plan, also when the plan changes between steps.
+A plan (stream chains; swarms, whole instances or whole kernel classes over
+the chains; eager launches or graphs of k iterations) changes only how
+iterations are launched: states must be bit-identical under every plan, also
+when the plan changes between steps.
 The tuner must leave the handle exactly in the state its initialisation made,
 on the plan it reports, and record that plan in the cache file named by
 QAP_SWARM_TUNE_CACHE, from which a new handle of the same workload starts.
@@ -44,7 +45,8 @@ def make(q, cs):
     return q.Swarm([(F, D) for F, D, _ in cs], [q.make_params(engine="fused", **c) for _, _, c in cs])
 
 
-PLANS = [(1, 0, 0), (2, 0, 1), (3, 0, 8), (4, 0, 8), (1, 1, 8), (2, 1, 0), (3, 1, 1), (4, 1, 8), (3, 0, 16)]
+PLANS = [(1, 0, 0), (2, 0, 1), (3, 0, 8), (4, 0, 8), (1, 1, 8), (2, 1, 0), (3, 1, 1), (4, 1, 8), (3, 0, 16),
+         (2, 2, 8), (4, 2, 0), (3, 2, 1)]
 
 
 def test_states_identical_under_every_plan(q):
