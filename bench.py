@@ -45,11 +45,11 @@ def algorithmic_bytes(stage: str, n: int) -> int:
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_n128x10k_traffic.md")
-KERNEL_SOURCES = ["common.hpp", "philox.hpp", "second_target.hpp", "kernels_fused.hip", "qap_swarm.hip"]
+KERNEL_SOURCES = ["common.hpp", "philox.hpp", "dword.hpp", "second_target.hpp", "kernels_fused.hip"]
 
 
 def kernel_hash() -> str:
-    """Hash of the sources the fused step kernel is built from."""
+    """Hash of the device sources the fused step kernel is built from."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1504_05158_amd", "csrc", f), "rb") as fh:
@@ -130,6 +130,8 @@ def run_gpu(args, engine: str):
     import paper_1504_05158_amd as q
 
     insts = workload_setup(args.workload)
+    if args.local_search is not None:
+        insts = [(A, B, dict(p, local_search=args.local_search)) for A, B, p in insts]
     F, D = insts[0][0], insts[0][1]
     n = F.shape[0]
     stream = torch.cuda.Stream()
@@ -250,11 +252,12 @@ def cpu_baseline(target_s: float = 15.0, max_steps: int = 50, threads: int = 16,
 
 def trace_span(path: str, args) -> dict:
     """Per-iteration span of the timed region in a rocprofv3 kernel trace
-    (csv) of `bench.py --no-compare --no-cpu-baseline --no-profile-pass`:
-    the dispatches that start after the last warm-up iteration has ended
-    (the k_finish dispatch number 1 + warmup x groups, by end time: one at
-    init, one per stream group per iteration), from the first start to the
-    last end, divided by the timed iterations."""
+    (csv) of `bench.py --no-compare --no-cpu-baseline --no-profile-pass`,
+    whose timed iterations are the last work it launches: the k_finish
+    dispatches (one per stream chain per iteration) of the timed iterations
+    are the last steps x chains of them by end time; the region is every
+    dispatch that starts after the k_finish before those, from the first
+    start to the last end, divided by the timed iterations."""
     import csv
     rows = []
     with open(path) as fh:
@@ -262,7 +265,7 @@ def trace_span(path: str, args) -> dict:
             rows.append((r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
     fin = sorted(e for name, b, e in rows if "k_finish" in name)
     groups = args.groups
-    cut = fin[args.warmup * groups]  # end of the last warm-up iteration
+    cut = fin[-args.steps * groups - 1]  # end of the last iteration before the timed ones
     timed = [(name, b, e) for name, b, e in rows if b > cut]
     span_ns = max(e for _, _, e in timed) - min(b for _, b, _ in timed)
     per_iter_ms = span_ns / 1e6 / args.steps
@@ -289,13 +292,16 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan instead of the tuned one")
+    ap.add_argument("--local-search", type=int, default=None,
+                    help="pair exchanges per particle-iteration instead of the workload's (1)")
     ap.add_argument("--no-profile-pass", action="store_true",
                     help="skip the second, event-timed run (for kernel traces of the timed region alone)")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="run only a 1 GiB device copy (for scaling HBM byte counters)")
     ap.add_argument("--trace-span", metavar="CSV",
                     help="no GPU run: the per-iteration span of the timed region in a rocprofv3 kernel trace")
-    ap.add_argument("--groups", type=int, default=3, help="with --trace-span: stream groups of the traced run")
+    ap.add_argument("--groups", type=int, default=3,
+                    help="with --trace-span: stream chains of the traced run (its JSON line's stream_groups)")
     args = ap.parse_args()
     if args.trace_span:
         print(json.dumps(trace_span(args.trace_span, args)))
@@ -347,6 +353,8 @@ def main():
     }
     if res["instances"] > 1:
         line["config"]["instances"] = res["instances"]
+    if args.local_search is not None:
+        line["config"]["local_search"] = args.local_search
     if other is not None:
         line["compare"] = {("plain" if args.engine == "fused" else "fused"):
                            (round(other["value"], 1) if "value" in other else other)}

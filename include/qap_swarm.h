@@ -289,6 +289,28 @@ enum { QAP_STATS_MAX_RANKS = 64, QAP_STATS_MAX_BINS = 4096 };
 int qap_swarm_stats(qap_swarm* h, int32_t instance, int32_t nq, const int32_t* q_ppm, int64_t* swarm_q,
                     int64_t* pop_q, int32_t bins, int64_t lo, int64_t hi, int64_t* swarm_hist, int64_t* pop_hist);
 
+/* Per-iteration statistics: the percentile ranks and PMFs of Sec. 4.2 (Figs.
+ * 4-7 follow them iteration by iteration), recorded on the device after
+ * every iteration of qap_swarm_step into a ring of `capacity` records
+ * (1..QAP_HISTORY_MAX_RECORDS) per instance, with the definitions of
+ * qap_swarm_stats (nq ranks q_ppm, bins over [lo, hi); at least one of nq,
+ * bins > 0).  Recording adds, after every iteration, one launch on the
+ * handle's stream once every stream chain has finished the iteration, and no
+ * host synchronisation; steps then replay single-iteration graphs.
+ * qap_swarm_history_start (re)starts recording (earlier records are
+ * dropped), qap_swarm_history_stop ends it and frees the ring.
+ * qap_swarm_history_read (waits) gives the latest min(max_records, records
+ * kept) iterations, oldest first: *count of them, their iteration numbers
+ * iters [count], swarm_q [count][m][nq], pop_q [count][nq],
+ * swarm_hist [count][m][bins], pop_hist [count][bins] (each may be NULL);
+ * QAP_ERR_INVALID_ARG if the instance is not recording. */
+enum { QAP_HISTORY_MAX_RECORDS = 1 << 20 };
+int qap_swarm_history_start(qap_swarm* h, int32_t instance, int32_t capacity, int32_t nq, const int32_t* q_ppm,
+                            int32_t bins, int64_t lo, int64_t hi);
+int qap_swarm_history_stop(qap_swarm* h, int32_t instance);
+int qap_swarm_history_read(qap_swarm* h, int32_t instance, int32_t max_records, int32_t* count, int32_t* iters,
+                           int64_t* swarm_q, int64_t* pop_q, int64_t* swarm_hist, int64_t* pop_hist);
+
 /* qap_swarm_stats for callers that cannot allocate memory (code under graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * arguments and results, computed without any device or host allocation.

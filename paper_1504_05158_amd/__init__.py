@@ -32,7 +32,8 @@ EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swar
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",
            "qap_swarm_deltas", "qap_swarm_path", "qap_swarm_graph", "qap_swarm_stats", "qap_swarm_profile",
            "qap_swarm_destroy", "qap_swarm_strerror", "qap_swarm_fail_alloc", "qap_swarm_live_allocations",
-           "qap_swarm_stats_noalloc", "qap_swarm_get_plan", "qap_swarm_set_plan", "qap_swarm_tune"]
+           "qap_swarm_stats_noalloc", "qap_swarm_get_plan", "qap_swarm_set_plan", "qap_swarm_tune",
+           "qap_swarm_history_start", "qap_swarm_history_stop", "qap_swarm_history_read"]
 STAGES = ["sx", "velocity", "goal_delta", "fused", "bests"]
 
 
@@ -98,6 +99,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                   P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                   P(ctypes.c_int64), P(ctypes.c_int64)]
     L.qap_swarm_stats_noalloc.argtypes = L.qap_swarm_stats.argtypes
+    L.qap_swarm_history_start.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32),
+                                          ctypes.c_int32, ctypes.c_int64, ctypes.c_int64]
+    L.qap_swarm_history_stop.argtypes = [vp, ctypes.c_int32]
+    L.qap_swarm_history_read.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_int32), P(ctypes.c_int32),
+                                         P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64), P(ctypes.c_int64)]
     L.qap_swarm_get_plan.argtypes = [vp, P(qap_plan)]
     L.qap_swarm_set_plan.argtypes = [vp, P(qap_plan)]
     L.qap_swarm_tune.argtypes = [vp, ctypes.c_int32, P(qap_plan)]
@@ -350,6 +356,36 @@ class Swarm:
                   _ptr(out["pop_hist"], ctypes.c_int64) if bins else None),
                "qap_swarm_stats_noalloc" if noalloc else "qap_swarm_stats")
         return out
+
+    def history_start(self, capacity: int, q_ppm=(50000, 250000, 500000, 750000), bins: int = 0, lo: int = 0,
+                      hi: int = 1, instance: int = 0) -> None:
+        """Record the percentile ranks and PMF counts after every iteration (a ring of `capacity` records)."""
+        q = np.ascontiguousarray(q_ppm, np.int32)
+        self._hist = getattr(self, "_hist", {})
+        self._hist[instance] = (len(q), int(bins), int(capacity))
+        _check(load_library().qap_swarm_history_start(self.h, instance, int(capacity), len(q),
+                                                      _ptr(q, ctypes.c_int32) if len(q) else None, int(bins),
+                                                      int(lo), int(hi)), "qap_swarm_history_start")
+
+    def history_stop(self, instance: int = 0) -> None:
+        _check(load_library().qap_swarm_history_stop(self.h, instance), "qap_swarm_history_stop")
+
+    def history_read(self, max_records: int | None = None, instance: int = 0) -> dict:
+        """The latest recorded iterations, oldest first."""
+        # an instance that is not recording: the library reports it
+        nq, bins, cap = getattr(self, "_hist", {}).get(instance, (0, 0, 0))
+        R = cap if max_records is None else int(max_records)
+        m = self.ms[instance]
+        out = dict(iters=np.zeros(R, np.int32), swarm_q=np.zeros((R, m, nq), np.int64), pop_q=np.zeros((R, nq), np.int64),
+                   swarm_hist=np.zeros((R, m, bins), np.int64), pop_hist=np.zeros((R, bins), np.int64))
+        cnt = ctypes.c_int32()
+        _check(load_library().qap_swarm_history_read(self.h, instance, R, ctypes.byref(cnt),
+                                                     _ptr(out["iters"], ctypes.c_int32),
+                                                     _ptr(out["swarm_q"], ctypes.c_int64), _ptr(out["pop_q"], ctypes.c_int64),
+                                                     _ptr(out["swarm_hist"], ctypes.c_int64),
+                                                     _ptr(out["pop_hist"], ctypes.c_int64)), "qap_swarm_history_read")
+        c = int(cnt.value)
+        return {k: v[:c] for k, v in out.items()}
 
     def profile(self, enable: bool):
         """Switch profiled stepping on/off; returns ({stage: ms}, iterations) so far."""

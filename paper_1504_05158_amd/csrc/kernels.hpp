@@ -84,6 +84,13 @@ hipError_t launch_select(const long long* values, const int* seg_off, int nseg, 
 hipError_t launch_hist(const long long* values, const int* seg_off, int nseg, int bins, long long lo, long long hi,
                        unsigned long long* out, hipStream_t st);
 
+// One record of the per-iteration statistics of an instance into slot
+// (*iter - 1) % capacity of its ring (see k_history).  All pointers are device
+// memory.
+hipError_t launch_history(const long long* goals, const int* iter, int m, int S, int nq, const long long* ranks,
+                          int bins, long long lo, long long hi, int capacity, int* ring_t, long long* ring_q,
+                          unsigned long long* ring_h, hipStream_t st);
+
 // The ranks of a statistics request in parts per million (passed by value).
 constexpr int kStatsMaxRanks = 64;
 struct StatsRanks {

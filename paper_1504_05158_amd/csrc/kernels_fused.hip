@@ -283,7 +283,7 @@ __device__ __forceinline__ float attract_cell(float c1, float x, DW o, float vma
 // row offsets go to the scalar offset, the lane's column to the vector one.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t matrix_rsrc(const float* p, int n)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, 4 * n * n, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, 4 * n * vld(n), 0x00020000);
 }
 
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
@@ -362,7 +362,7 @@ __device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdg
                                                float& m1, int& r1, float& m2, float& vx)
 {
     constexpr int B = 32;
-    const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)n;
+    const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)vld(n);
     DW sum{0.0f, 0.0f};
     int r0 = 0;
     for (; r0 + B <= n; r0 += B) {
@@ -450,8 +450,8 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
     const int cur = tprev & 1;
     const int gs = k / d.S;  // swarm within this descriptor; g: within the instance
     const uint32_t g = (uint32_t)(gs + d.swarm_base), s = (uint32_t)(k % d.S);
-    global_t<const float>* Vp = gl(buf(d.V, cur)) + (size_t)k * n * n;
-    float* Vq = buf(d.V, cur ^ 1) + (size_t)k * n * n;  // buffer stores
+    global_t<const float>* Vp = gl(buf(d.V, cur)) + (size_t)k * n * vld(n);
+    float* Vq = buf(d.V, cur ^ 1) + (size_t)k * n * vld(n);  // buffer stores
     global_t<const uint8_t>* Xk = gl(buf(d.X, cur)) + (size_t)k * n;
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
     // c2 r2, c3 r3 (exact double words) and their sum: the attraction terms

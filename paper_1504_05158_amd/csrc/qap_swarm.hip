@@ -42,6 +42,13 @@ struct Instance {
     int mul24 = 0;
     bool stepped = false;         // a step ran since init / set_state: the buffers of the previous state hold it
     long long t = 0;              // completed iterations (host copy of the device counter)
+    // per-iteration statistics (qap_swarm_history_start): ring of records
+    int hist_cap = 0, hist_nq = 0, hist_bins = 0;
+    long long hist_lo = 0, hist_hi = 1, hist_t0 = 0;  // hist_t0: iteration when recording started
+    long long* hist_ranks = nullptr;       // device [(m + 1) nq]
+    int* ring_t = nullptr;                 // device [cap]
+    long long* ring_q = nullptr;           // device [cap][m + 1][nq]
+    unsigned long long* ring_h = nullptr;  // device [cap][m + 1][bins]
     int* order = nullptr;         // [m] migration ranking scratch
     int groups = 1;               // swarm groups of the instance under the current plan
     std::vector<InstDesc> gdesc;  // [groups] descriptor of each group's swarms
@@ -188,8 +195,22 @@ hipError_t dalloc(Instance& I, T** p, size_t count)
     return hipSuccess;
 }
 
+void free_history(Instance& I)
+{
+    dev_free(I.hist_ranks);
+    dev_free(I.ring_t);
+    dev_free(I.ring_q);
+    dev_free(I.ring_h);
+    I.hist_ranks = nullptr;
+    I.ring_t = nullptr;
+    I.ring_q = nullptr;
+    I.ring_h = nullptr;
+    I.hist_cap = 0;
+}
+
 void free_instance(Instance& I)
 {
+    free_history(I);
     for (void* p : I.allocs) dev_free(p);
     I.allocs.clear();
 }
@@ -358,8 +379,9 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
             *hi[m] = H;
         }
     }
-    TRY(dalloc(I, &d.V[0], P * nn));
-    TRY(dalloc(I, &d.V[1], P * nn));
+    const size_t nv = (size_t)n * qap::vld(n);  // padded rows
+    TRY(dalloc(I, &d.V[0], P * nv));
+    TRY(dalloc(I, &d.V[1], P * nv));
     TRY(dalloc(I, &d.Vinv[0], P * n));
     TRY(dalloc(I, &d.Vinv[1], P * n));
     TRY(dalloc(I, &d.X[0], P * n));
@@ -412,7 +434,7 @@ int init_state(qap_swarm* h, Instance& I)
 void make_groups(Instance& I, int groups)
 {
     const InstDesc& d = I.d;
-    const size_t n = (size_t)I.n, nn = n * n;
+    const size_t n = (size_t)I.n, nv = n * qap::vld(I.n);  // padded V rows
     I.groups = groups;
     I.gdesc.clear();
     for (int j = 0, g0 = 0; j < I.groups; ++j) {
@@ -423,7 +445,7 @@ void make_groups(Instance& I, int groups)
         gd.m = mj;
         gd.P = mj * I.S;
         for (int b = 0; b < 2; ++b) {
-            gd.V[b] = d.V[b] + p0 * nn;
+            gd.V[b] = d.V[b] + p0 * nv;
             gd.Vinv[b] = d.Vinv[b] + p0 * n;
             gd.X[b] = d.X[b] + p0 * n;
         }
@@ -1053,7 +1075,9 @@ int impl_step(qap_swarm* h, int32_t iterations)
         // a graph of several iterations where no migration join falls inside it
         const int K = h->cfg.ipg;
         const bool graphs = !h->profiling && K > 0 && !h->graph_failed;
-        const bool multi = graphs && K > 1 && iterations - it >= K && !migration_due(h, it, K);
+        bool record = false;  // some instance records its statistics after every iteration
+        for (const Instance& I : h->inst) record = record || I.hist_cap > 0;
+        const bool multi = graphs && K > 1 && iterations - it >= K && !migration_due(h, it, K) && !record;
         const int chunk = multi ? K : 1;
         for (int j = 0; j < G; ++j) {
             hipGraphExec_t* gx = multi ? &h->graphs_k[(size_t)j] : &h->graphs[(size_t)j];
@@ -1072,12 +1096,23 @@ int impl_step(qap_swarm* h, int32_t iterations)
         // Alg. 2 of the instances stepped in several groups, when due (only
         // after single iterations): the groups join, one launch migrates, and
         // they fork again before the next iteration reads P^G
-        if (!multi && migration_due(h, it, 1)) {
+        // and the per-iteration statistics of the recording instances (on
+        // the handle's stream, once every chain finished the iteration; no
+        // host synchronisation)
+        const bool mig = !multi && migration_due(h, it, 1);
+        if (mig || record) {
             for (int j = 1; j < G && e == hipSuccess; ++j) {
                 e = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
                 if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
             }
-            if (e == hipSuccess) e = qap::launch_migrate(h->migr_descs, (int)h->migr.size(), h->stream);
+            if (e == hipSuccess && mig) e = qap::launch_migrate(h->migr_descs, (int)h->migr.size(), h->stream);
+            for (size_t k = 0; k < h->inst.size() && e == hipSuccess && record; ++k) {
+                const Instance& I = h->inst[k];
+                if (I.hist_cap > 0)
+                    e = qap::launch_history(I.d.goal, I.d.iter, I.m, I.S, I.hist_nq, I.hist_ranks, I.hist_bins,
+                                            I.hist_lo, I.hist_hi, I.hist_cap, I.ring_t, I.ring_q, I.ring_h,
+                                            h->stream);
+            }
             if (e == hipSuccess) e = hipEventRecord(h->gevent[0], h->stream);
             for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
             if (e != hipSuccess) return dev_err(h, e);
@@ -1163,7 +1198,8 @@ int impl_get_state(qap_swarm* h, int32_t instance, qap_state* st)
     if (e == hipSuccess && st->V) {
         // V = fl(U * scale) per column, the value every kernel reads
         std::vector<float> sc(P * n);
-        e = hipMemcpy(st->V, d.V[cur], P * n * n * sizeof(float), hipMemcpyDeviceToHost);
+        e = hipMemcpy2D(st->V, n * sizeof(float), d.V[cur], (size_t)qap::vld((int)n) * sizeof(float), n * sizeof(float),
+                        P * n, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(sc.data(), d.Vinv[cur], P * n * sizeof(float), hipMemcpyDeviceToHost);
         if (e == hipSuccess)
             for (size_t k = 0; k < P; ++k)
@@ -1223,7 +1259,9 @@ int impl_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
         for (size_t i = 0; i < rows * n; ++i) buf[i] = (uint8_t)src[i];
         return hipMemcpy(dst, buf.data(), rows * n, hipMemcpyHostToDevice);
     };
-    if (e == hipSuccess) e = hipMemcpy(d.V[cur], st->V, P * n * n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy2D(d.V[cur], (size_t)qap::vld((int)n) * sizeof(float), st->V, n * sizeof(float), n * sizeof(float),
+                        P * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         const std::vector<float> ones(P * n, 1.0f);
         e = hipMemcpy(d.Vinv[cur], ones.data(), P * n * sizeof(float), hipMemcpyHostToDevice);
@@ -1480,6 +1518,101 @@ int impl_stats_noalloc(qap_swarm* h, int32_t instance, int32_t nq, const int32_t
     return dev_err(h, e);
 }
 
+int impl_history_start(qap_swarm* h, int32_t instance, int32_t capacity, int32_t nq, const int32_t* q_ppm,
+                       int32_t bins, int64_t lo, int64_t hi)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (capacity < 1 || capacity > QAP_HISTORY_MAX_RECORDS) return QAP_ERR_INVALID_ARG;
+    if (nq < 0 || nq > QAP_STATS_MAX_RANKS || (nq > 0 && !q_ppm)) return QAP_ERR_INVALID_ARG;
+    for (int j = 0; j < nq; ++j)
+        if (q_ppm[j] < 1 || q_ppm[j] > 1000000) return QAP_ERR_INVALID_ARG;
+    if (bins < 0 || bins > QAP_STATS_MAX_BINS || (nq == 0 && bins == 0)) return QAP_ERR_INVALID_ARG;
+    if (bins > 0 && (!(lo < hi) || (unsigned long long)hi - (unsigned long long)lo > (1ull << 62) / (unsigned)bins))
+        return QAP_ERR_INVALID_ARG;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return dev_err(h, e);
+    free_history(*I);
+    const int m = I->m;
+    std::vector<long long> ranks((size_t)(m + 1) * std::max(nq, 1), 1);
+    for (int g = 0; g <= m; ++g)
+        for (int j = 0; j < nq; ++j) {
+            const long long N = g < m ? I->S : I->P;
+            ranks[(size_t)g * nq + j] = std::max(1LL, ((long long)q_ppm[j] * N + 999999) / 1000000);
+        }
+    const size_t cap = (size_t)capacity;
+    e = dev_malloc(reinterpret_cast<void**>(&I->hist_ranks), sizeof(long long) * ranks.size());
+    if (e == hipSuccess) e = dev_malloc(reinterpret_cast<void**>(&I->ring_t), sizeof(int) * cap);
+    if (e == hipSuccess)
+        e = dev_malloc(reinterpret_cast<void**>(&I->ring_q), sizeof(long long) * cap * (m + 1) * std::max(nq, 1));
+    if (e == hipSuccess)
+        e = dev_malloc(reinterpret_cast<void**>(&I->ring_h), sizeof(long long) * cap * (m + 1) * std::max(bins, 1));
+    if (e == hipSuccess) e = hipMemcpy(I->hist_ranks, ranks.data(), sizeof(long long) * ranks.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(I->ring_t, 0, sizeof(int) * cap);
+    if (e != hipSuccess) {
+        free_history(*I);
+        return dev_err(h, e);
+    }
+    I->hist_cap = capacity;
+    I->hist_nq = nq;
+    I->hist_bins = bins;
+    I->hist_lo = lo;
+    I->hist_hi = hi;
+    I->hist_t0 = I->t;
+    return QAP_OK;
+}
+
+int impl_history_stop(qap_swarm* h, int32_t instance)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    free_history(*I);
+    return dev_err(h, e);
+}
+
+int impl_history_read(qap_swarm* h, int32_t instance, int32_t max_records, int32_t* count, int32_t* iters,
+                      int64_t* swarm_q, int64_t* pop_q, int64_t* swarm_hist, int64_t* pop_hist)
+{
+    Instance* I;
+    int rc = get_instance(h, instance, &I);
+    if (rc != QAP_OK) return rc;
+    if (!count || max_records < 0) return QAP_ERR_INVALID_ARG;
+    *count = 0;
+    if (I->hist_cap == 0) return QAP_ERR_INVALID_ARG;  // not recording
+    const int m = I->m, nq = I->hist_nq, bins = I->hist_bins, cap = I->hist_cap;
+    const long long recorded = std::min<long long>(I->t - I->hist_t0, cap);
+    const int want = (int)std::min<long long>(recorded, max_records);
+    if (want == 0) return QAP_OK;
+    const size_t rq = (size_t)(m + 1) * std::max(nq, 1), rh = (size_t)(m + 1) * std::max(bins, 1);
+    std::vector<int> rt((size_t)cap);
+    std::vector<long long> q((size_t)cap * rq);
+    std::vector<unsigned long long> hh((size_t)cap * rh);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e == hipSuccess) e = hipMemcpy(rt.data(), I->ring_t, sizeof(int) * cap, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && nq > 0) e = hipMemcpy(q.data(), I->ring_q, sizeof(long long) * q.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && bins > 0) e = hipMemcpy(hh.data(), I->ring_h, sizeof(long long) * hh.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return dev_err(h, e);
+    // the latest `want` iterations, oldest first: iteration t sits in slot (t - 1) % cap
+    for (int r = 0; r < want; ++r) {
+        const long long t = I->t - want + 1 + r;
+        const size_t slot = (size_t)((t - 1) % cap);
+        if (rt[slot] != (int)t) return QAP_ERR_DEVICE;  // a record that was not written
+        if (iters) iters[r] = (int32_t)t;
+        for (int g = 0; g < m; ++g) {
+            for (int j = 0; j < nq && swarm_q; ++j) swarm_q[((size_t)r * m + g) * nq + j] = q[slot * rq + (size_t)g * nq + j];
+            for (int b = 0; b < bins && swarm_hist; ++b)
+                swarm_hist[((size_t)r * m + g) * bins + b] = (int64_t)hh[slot * rh + (size_t)g * bins + b];
+        }
+        for (int j = 0; j < nq && pop_q; ++j) pop_q[(size_t)r * nq + j] = q[slot * rq + (size_t)m * nq + j];
+        for (int b = 0; b < bins && pop_hist; ++b) pop_hist[(size_t)r * bins + b] = (int64_t)hh[slot * rh + (size_t)m * bins + b];
+    }
+    *count = want;
+    return QAP_OK;
+}
+
 int impl_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     if (!h) return QAP_ERR_INVALID_ARG;
@@ -1540,7 +1673,7 @@ int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
     if (h->sticky != QAP_OK) return h->sticky;
     if (h->profiling) return QAP_ERR_INVALID_ARG;
     for (const Instance& I : h->inst)
-        if (I.t != 0 || I.stepped) return QAP_ERR_INVALID_ARG;  // tuning starts from iteration 0
+        if (I.t != 0 || I.stepped || I.hist_cap > 0) return QAP_ERR_INVALID_ARG;  // from iteration 0, not recording
     std::vector<PlanCfg> cands;
     const bool several = h->inst.size() > 1;
     for (int split = 0; split <= (several ? 2 : 0); ++split)
@@ -1769,6 +1902,39 @@ int qap_swarm_graph(qap_swarm* h, int32_t* active, int32_t* streams)
 {
     try {
         return impl_graph(h, active, streams);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_history_start(qap_swarm* h, int32_t instance, int32_t capacity, int32_t nq, const int32_t* q_ppm,
+                            int32_t bins, int64_t lo, int64_t hi)
+{
+    try {
+        return impl_history_start(h, instance, capacity, nq, q_ppm, bins, lo, hi);
+    } catch (const std::bad_alloc&) {
+        return QAP_ERR_NOMEM;
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_history_stop(qap_swarm* h, int32_t instance)
+{
+    try {
+        return impl_history_stop(h, instance);
+    } catch (...) {
+        return QAP_ERR_DEVICE;
+    }
+}
+
+int qap_swarm_history_read(qap_swarm* h, int32_t instance, int32_t max_records, int32_t* count, int32_t* iters,
+                           int64_t* swarm_q, int64_t* pop_q, int64_t* swarm_hist, int64_t* pop_hist)
+{
+    try {
+        return impl_history_read(h, instance, max_records, count, iters, swarm_q, pop_q, swarm_hist, pop_hist);
     } catch (const std::bad_alloc&) {
         return QAP_ERR_NOMEM;
     } catch (...) {
