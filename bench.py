@@ -21,6 +21,14 @@ import re
 import sys
 import time
 
+# Concurrent stream chains overlap only on hardware queues of their own: HIP
+# gives a process 4 by default, shared by every stream it creates (the default
+# stream and the caller's included), and kernels of two streams on one queue
+# run one after the other.  Ask for at least 8 (set before HIP starts).
+HW_QUEUES = 8
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < HW_QUEUES:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(HW_QUEUES)
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -143,7 +151,11 @@ def run_gpu(args, engine: str):
         nonlocal plan
         prms = [q.make_params(stream=stream.cuda_stream, engine=engine, **p) for _, _, p in insts]
         h = q.Swarm([(A, B) for A, B, _ in insts], prms)
-        if not args.no_tune:
+        if args.plan:
+            c, s_, i = (int(x) for x in args.plan.split(","))
+            h.set_plan(c, s_, i)
+            plan = h.plan()
+        elif not args.no_tune:
             # the launch plan is chosen on the handle's own work and the handle
             # returned to iteration 0: set-up, before the timed region
             if plan is None:
@@ -292,6 +304,9 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip timing the per-stage (plain int32) engine")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan instead of the tuned one")
+    ap.add_argument("--plan", metavar="C,S,I", default=None,
+                    help="launch plan to use instead of tuning: stream chains, split (0 swarms, 1 instances, "
+                         "2 kernel classes), iterations per graph (0 = eager)")
     ap.add_argument("--local-search", type=int, default=None,
                     help="pair exchanges per particle-iteration instead of the workload's (1)")
     ap.add_argument("--no-profile-pass", action="store_true",
@@ -350,6 +365,7 @@ def main():
         "stage_ms": res["stage_ms"],
         "stream_groups": res["groups"],
         "plan": res["plan"],
+        "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"]),
     }
     if res["instances"] > 1:
         line["config"]["instances"] = res["instances"]

@@ -185,7 +185,10 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  * A plan says how the iterations of a handle are launched; results are
  * bit-identical under every plan.
  *   stream_chains: concurrent chains of launches, each on its own stream
- *     (1..QAP_MAX_CHAINS; the device has 4 hardware queues per process).
+ *     (1..QAP_MAX_CHAINS).  Chain 0 runs on the handle's stream.  A process's
+ *     streams share the HIP runtime's hardware queues (GPU_MAX_HW_QUEUES, 4
+ *     by default) and kernels of two streams on one queue run one after the
+ *     other: k chains overlap fully with k + 1 queues or more.
  *   split: QAP_SPLIT_SWARMS -- every instance's swarms are spread over the
  *     chains (an instance whose stream_groups parameter is set keeps that many
  *     groups at most); QAP_SPLIT_INSTANCES -- whole instances, the heaviest
@@ -203,11 +206,12 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  * (QAP_ERR_INVALID_ARG for a plan outside the ranges above).
  * qap_swarm_tune times every plan (chains 1..4 x split x {eager, 1, 8}
  * iterations per graph; the instance and class splits only for several
- * instances) on the
- * handle's own work, each from iteration 0 -- 10 iterations of warm-up, then
- * trial_iterations (1..4096) between events -- keeps the fastest, and returns
- * the handle to iteration 0 (the state init made, re-created from the seed).  It must be called before the
- * first step (QAP_ERR_INVALID_ARG otherwise).  If the environment variable
+ * instances) on the handle's own work, each from iteration 0 -- 10
+ * iterations of warm-up, then trial_iterations (1..4096) between events --
+ * then times the 4 fastest again on 2 x trial_iterations, keeps the fastest
+ * of that round, and returns the handle to iteration 0 (the state init made,
+ * re-created from the seed).  It must be called before the first step
+ * (QAP_ERR_INVALID_ARG otherwise).  If the environment variable
  * QAP_SWARM_TUNE_CACHE names a file, the choice is appended to it under a
  * signature of the device and the workload, and later handles with the same
  * signature start on it without timing. */

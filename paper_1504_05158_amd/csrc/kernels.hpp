@@ -41,7 +41,7 @@ hipError_t launch_migrate(const InstDesc* descs, int count, hipStream_t st);
 // host descriptor `one` (a kernel argument); otherwise one = NULL and descs
 // [instances of the class] and blkmap [blocks] (workgroup -> (class-local
 // instance, first particle)) are device tables.  Bests follow separately.
-// wide: 0 int8, 1 byte-split with one matrix split, 2 both split.
+// wide: 0 int8, else the byte-split pattern (1 F split, 2 D split, 3 both).
 hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstDesc* one, const InstDesc* descs,
                               const int2* blkmap, int blocks, hipStream_t st);
 
@@ -49,15 +49,15 @@ hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstD
 // workgroup share one LDS copy of F and D.  Larger workgroups where LDS, not
 // registers, limited the kernel: the npad-160 int8 symmetric kernels (F, D and
 // the per-wave data take 59 KB per 4-wave workgroup: 2 per CU, while the
-// registers allow 3 waves per SIMD) take 12 waves, as does the byte-split
-// npad-128 kernel with zero diagonals (four planes, 79 KB per 4-wave
-// workgroup); the byte-split npad-160 kernels (116 KB: one 4-wave workgroup
-// per CU) take 8, which they hold without spilling.  4 elsewhere.
+// registers allow 3 waves per SIMD) take 12 waves; the byte-split kernels with
+// one matrix split take 8 at npad 128 with zero diagonals (three planes and 8
+// waves' data: 64 KB, 2 workgroups per CU, 4 waves per SIMD as the registers
+// allow) and at npad 160 (one workgroup per CU).  4 elsewhere.
 constexpr int fused_wpb(int npad, int wide, bool sym, bool zd)
 {
-    return (wide == 0 && sym && npad == 160) || (wide == 1 && npad == 128 && zd) ? 12
-           : (wide == 1 && npad == 160)                                          ? 8
-                                                                                   : 4;
+    return (wide == 0 && sym && npad == 160)                                                     ? 12
+           : ((wide == 1 || wide == 2) && npad == 128 && zd) || ((wide == 1 || wide == 2) && npad == 160) ? 8
+                                                                                                            : 4;
 }
 int fused_particles_per_block(int npad, int wide, bool sym, bool zd);
 

@@ -637,7 +637,9 @@ __global__ __launch_bounds__(64 * WPB) void k_fused_step(InstDesc one, const Ins
 // Fq[y][l] = F[y][q_l] gathered, q = p^-1, since A[x][y] = sum_l F[x][q_l]
 // D[p_y][l].  The gathered operand is held in registers for every block; form
 // 1 is taken when only D is split, so that the held operand stays one plane.
-// HS (both matrices split) holds two planes: twice the registers.
+// Both matrices split (SPLIT 3) holds two planes: twice the registers.
+// SPLIT, the split pattern, is a template parameter (bit 0: F split, bit 1: D
+// split), so the plane reads of the pair scan carry no branches.
 // For symmetric F and D the deltas use A_xy + A_yx only, which both forms
 // accumulate in one tile.
 
@@ -657,48 +659,69 @@ struct WideWaveLds {
     } u;
 };
 
-template <int NP>
+// Byte planes of the wide path in LDS, NP rows of lds_stride bytes each.
+// Both matrices split: F low, F high, D low, D high.  One matrix split: three
+// planes, the split matrix's low and high planes first, then the other
+// matrix's low plane.  The high plane of a split matrix lies one plane after
+// its low plane.
+template <int SPLIT>
+constexpr int wide_planes() { return SPLIT == 3 ? 4 : 3; }
+
+// Offsets of F's and D's low planes.
+template <int NP, int SPLIT>
+constexpr int wide_f_off() { return SPLIT == 2 ? 2 * NP * lds_stride<NP>() : 0; }
+template <int NP, int SPLIT>
+constexpr int wide_d_off() { return SPLIT == 2 ? 0 : 2 * NP * lds_stride<NP>(); }
+
+template <int NP, int SPLIT>
 __device__ __forceinline__ void load_wide_lds(const InstDesc& d, int8_t* pl)
 {
     constexpr int LS = lds_stride<NP>(), PS = NP * LS, RV = NP / 16;
+    int8_t* fl = pl + wide_f_off<NP, SPLIT>();
+    int8_t* dl = pl + wide_d_off<NP, SPLIT>();
     global_t<const v4i>* src[4] = {reinterpret_cast<global_t<const v4i>*>(gl(d.F8)), reinterpret_cast<global_t<const v4i>*>(gl(d.FH8)),
                                    reinterpret_cast<global_t<const v4i>*>(gl(d.D8)), reinterpret_cast<global_t<const v4i>*>(gl(d.DH8))};
-    const bool on[4] = {true, (d.split & 1) != 0, true, (d.split & 2) != 0};
+    int8_t* dst[4] = {fl, fl + PS, dl, dl + PS};
+    constexpr bool on[4] = {true, (SPLIT & 1) != 0, true, (SPLIT & 2) != 0};
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if (!on[m]) continue;
         for (int i = threadIdx.x; i < NP * RV; i += blockDim.x)
-            *reinterpret_cast<v4i*>(pl + m * PS + (i / RV) * LS + 16 * (i % RV)) = src[m][i];
+            *reinterpret_cast<v4i*>(dst[m] + (i / RV) * LS + 16 * (i % RV)) = src[m][i];
     }
 }
 
-// Entry off of a matrix from its low plane (and the high plane PS bytes on).
-template <int PS>
-__device__ __forceinline__ int wide_val(const int8_t* lo, int off, bool split)
+// Entry off of a matrix from its low plane (and, if SPLIT, the high plane PS
+// bytes on).
+template <int PS, bool SPLIT>
+__device__ __forceinline__ int wide_val(const int8_t* lo, int off)
 {
     int v = lo[off];
-    if (split) v += 128 * (int)lo[off + PS];
+    if constexpr (SPLIT) v += 128 * (int)lo[off + PS];
     return v;
 }
 
 // Stage C of the wide path for one permutation sp (NP bytes, zero beyond n);
 // sq receives q = p^-1 when form 1 is used.  Same results as goal_delta_mfma.
-// HS must equal (split == 3).
-template <int NP, bool ZD, bool HS>
-__device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_t* sp, uint8_t* sq, RowW* sri,
+// SPLIT must equal the instance's split pattern.
+template <int NP, bool ZD, int SPLIT>
+__device__ void goal_delta_wide(int n, const int8_t* pl, const uint8_t* sp, uint8_t* sq, RowW* sri,
                                 bool want_pairs, long long* dout, long long& goal, long long& bestkey)
 {
     constexpr int T = NP / 32, LS = lds_stride<NP>(), PS = NP * LS;
+    constexpr bool HS = SPLIT == 3;
     const int l = lane_id(), h = l >> 5, lc = l & 31;
-    const bool fs = HS || (split & 1) != 0, ds = HS || (split & 2) != 0;
-    const bool form = !HS && ds && !fs;
-    const int8_t* hl = pl + (form ? 0 : 2 * PS);  // held (gathered) operand, low plane
+    constexpr bool fs = (SPLIT & 1) != 0, ds = (SPLIT & 2) != 0;
+    constexpr bool form = SPLIT == 2;
+    const int8_t* fl = pl + wide_f_off<NP, SPLIT>();  // F, low plane (high plane PS bytes on)
+    const int8_t* dl = pl + wide_d_off<NP, SPLIT>();  // D, likewise
+    const int8_t* hl = form ? fl : dl;  // held (gathered) operand, low plane
     const int8_t* hh = hl + PS;
-    const int8_t* rl = pl + (form ? 2 * PS : 0);  // direct operand, low plane
+    const int8_t* rl = form ? dl : fl;  // direct operand, low plane
     const int8_t* rh = rl + PS;
     constexpr bool hs = HS;
-    const bool rs = form || fs;
-    if (form) {
+    constexpr bool rs = form || fs;
+    if constexpr (form) {
         for (int j = l; j < NP; j += kWave) {
             if (j < n) sq[sp[j]] = (uint8_t)j;
             else sq[j] = 0;
@@ -731,7 +754,7 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
             for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hh[a][kc], acc);
             acc *= 128;
         }
-        if (rs) {
+        if constexpr (rs) {
 #pragma unroll
             for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hl[a][kc], acc);
         }
@@ -739,7 +762,7 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
 #pragma unroll
             for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hh[a][kc], acc);
         }
-        if (rs || hs) acc *= 128;
+        if constexpr (rs || hs) acc *= 128;
 #pragma unroll
         for (int kc = 0; kc < T; ++kc) acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hl[a][kc], acc);
         if (h == ((lc >> 2) & 1)) {
@@ -753,8 +776,8 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                 gsum += da;
                 const int px = sp[x];
                 RowW ri;
-                ri.f = (short)wide_val<PS>(pl, x * LS + x, fs);
-                ri.dp = (short)wide_val<PS>(pl + 2 * PS, px * LS + px, ds);
+                ri.f = (short)wide_val<PS, fs>(fl, x * LS + x);
+                ri.dp = (short)wide_val<PS, ds>(dl, px * LS + px);
                 ri.da = 2 * da;
                 sri[x] = ri;
             }
@@ -780,7 +803,7 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                 }
                 acc *= 128;
             }
-            if (rs) {
+            if constexpr (rs) {
 #pragma unroll
                 for (int kc = 0; kc < T; ++kc) {
                     acc = mfma32(frag16<LS>(rh, ra, 32 * kc + 16 * h), Hl[b][kc], acc);
@@ -794,7 +817,7 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                     acc = mfma32(Hh[a][kc], frag16<LS>(rl, rb, 32 * kc + 16 * h), acc);
                 }
             }
-            if (rs || hs) acc *= 128;
+            if constexpr (rs || hs) acc *= 128;
 #pragma unroll
             for (int kc = 0; kc < T; ++kc) {
                 acc = mfma32(frag16<LS>(rl, ra, 32 * kc + 16 * h), Hl[b][kc], acc);
@@ -812,8 +835,8 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                 if (a == b && x >= y) continue;  // diagonal tiles: x < y only
                 const RowW rx = sri[x];
                 const int px = sp[x];
-                const int fxy = wide_val<PS>(pl, x * LS + y, fs);
-                const int dxy = wide_val<PS>(pl + 2 * PS, __umul24(px, LS) + py, ds);
+                const int fxy = wide_val<PS, fs>(fl, x * LS + y);
+                const int dxy = wide_val<PS, ds>(dl, __umul24(px, LS) + py);
                 const int base = 2 * acc[i] - rx.da - cy.da;
                 int del;
                 if constexpr (ZD)
@@ -827,6 +850,9 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
                 const bool lt = del < tmin;
                 tmin = lt ? del : tmin;
                 ti = lt ? i : ti;
+                // keep the running (minimum, index) pair in registers: otherwise
+                // the compiler keeps all 16 deltas to recover the index at the end
+                asm volatile("" : "+v"(tmin), "+v"(ti));
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (tmin != INT_MAX) {
@@ -840,13 +866,13 @@ __device__ void goal_delta_wide(int n, int split, const int8_t* pl, const uint8_
     bestkey = wave_min_i64(bestkey);
 }
 
-template <int NP, bool ZD, bool HS, int WPB>
+template <int NP, bool ZD, int SPLIT, int WPB>
 __device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
 {
     constexpr int CPL = cols_per_lane<NP>();
-    __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t spl[wide_planes<SPLIT>() * NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[WPB];
-    load_wide_lds<NP>(d, spl);
+    load_wide_lds<NP, SPLIT>(d, spl);
     __syncthreads();
 
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
@@ -858,21 +884,21 @@ __device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
     long long goal;
     int ba, bb;
     exchanges(d, pw, [&](long long& g, long long& key) {
-        goal_delta_wide<NP, ZD, HS>(d.n, d.split, spl, pw, sw[w].q, sw[w].u.ri, d.ls != 0, nullptr, g, key);
+        goal_delta_wide<NP, ZD, SPLIT>(d.n, spl, pw, sw[w].q, sw[w].u.ri, d.ls != 0, nullptr, g, key);
     }, goal, ba, bb);
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
-template <int NP, bool ZD, bool HS, bool TABLE, int WPB>
+template <int NP, bool ZD, int SPLIT, bool TABLE, int WPB>
 __global__ __launch_bounds__(64 * WPB) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
                                                          const int2* __restrict__ blkmap)
 {
     if constexpr (TABLE) {
         const int2 bm = blkmap[blockIdx.x];
-        fused_wide_block<NP, ZD, HS, WPB>(descs[__builtin_amdgcn_readfirstlane(bm.x)],
-                                          __builtin_amdgcn_readfirstlane(bm.y));
+        fused_wide_block<NP, ZD, SPLIT, WPB>(descs[__builtin_amdgcn_readfirstlane(bm.x)],
+                                             __builtin_amdgcn_readfirstlane(bm.y));
     } else {
-        fused_wide_block<NP, ZD, HS, WPB>(one, (int)blockIdx.x * WPB);
+        fused_wide_block<NP, ZD, SPLIT, WPB>(one, (int)blockIdx.x * WPB);
     }
 }
 
@@ -904,14 +930,14 @@ __global__ __launch_bounds__(256) void k_eval_mfma(InstDesc d, const uint8_t* __
     if (l == 0) goals[e] = goal;
 }
 
-template <int NP, bool ZD, bool HS>
+template <int NP, bool ZD, int SPLIT>
 __global__ __launch_bounds__(256) void k_eval_wide(InstDesc d, const uint8_t* __restrict__ perms, int count,
                                                    long long* __restrict__ goals, long long* __restrict__ deltas)
 {
     constexpr int CPL = cols_per_lane<NP>();
-    __shared__ __attribute__((aligned(16))) int8_t spl[4 * NP * lds_stride<NP>()];
+    __shared__ __attribute__((aligned(16))) int8_t spl[wide_planes<SPLIT>() * NP * lds_stride<NP>()];
     __shared__ __attribute__((aligned(16))) WideWaveLds<NP, CPL> sw[kWaves];
-    load_wide_lds<NP>(d, spl);
+    load_wide_lds<NP, SPLIT>(d, spl);
     __syncthreads();
     const int w = threadIdx.x / kWave, l = lane_id();
     const int e = blockIdx.x * kWaves + w;
@@ -922,7 +948,7 @@ __global__ __launch_bounds__(256) void k_eval_wide(InstDesc d, const uint8_t* __
     wave_sync();
     long long* dout = deltas ? deltas + (size_t)e * n * n : nullptr;
     long long goal, key;
-    goal_delta_wide<NP, ZD, HS>(n, d.split, spl, pw, sw[w].q, sw[w].u.ri, dout != nullptr, dout, goal, key);
+    goal_delta_wide<NP, ZD, SPLIT>(n, spl, pw, sw[w].q, sw[w].u.ri, dout != nullptr, dout, goal, key);
     if (dout)
         for (int j = l; j < n; j += kWave) dout[(size_t)j * n + j] = 0;
     if (l == 0) goals[e] = goal;
@@ -930,22 +956,22 @@ __global__ __launch_bounds__(256) void k_eval_wide(InstDesc d, const uint8_t* __
 
 // ------------------------------------------------------------------ launchers
 // Contraction variants: int8 general (F or D not symmetric), int8 symmetric,
-// int8 symmetric with zero diagonals, and the byte-split symmetric ones (WIDE 1:
-// one matrix split, 2: both; both split at npad 160 would not fit the register
-// file and is left to the int32 path).
+// int8 symmetric with zero diagonals, and the byte-split symmetric ones (WIDE =
+// the split pattern: 1 F split, 2 D split, 3 both; both split at npad 160 would
+// not fit the register file and is left to the int32 path).
 template <int NP, int WIDE, bool SYM, bool ZD>
 static hipError_t fused_launch_one(const InstDesc* one, const InstDesc* descs, const int2* blkmap, int blocks,
                                    hipStream_t st)
 {
     constexpr int WPB = fused_wpb(NP, WIDE, SYM, ZD);
     const dim3 grid((unsigned)blocks), block(WPB * kWave);
-    if constexpr (WIDE == 2 && NP > 128) {
+    if constexpr (WIDE == 3 && NP > 128) {
         return hipErrorNotSupported;
     } else if constexpr (WIDE != 0) {
         if (one)
-            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, false, WPB>), grid, block, 0, st, *one, descs, blkmap);
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE, false, WPB>), grid, block, 0, st, *one, descs, blkmap);
         else
-            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE == 2, true, WPB>), grid, block, 0, st, InstDesc{}, descs,
+            hipLaunchKernelGGL((k_fused_wide<NP, ZD, WIDE, true, WPB>), grid, block, 0, st, InstDesc{}, descs,
                                blkmap);
     } else {
         if (one)
@@ -983,14 +1009,16 @@ hipError_t launch_fused_class(int npad, int wide, bool sym, bool zd, const InstD
                               const int2* blkmap, int blocks, hipStream_t st)
 {
     if (blocks <= 0) return hipSuccess;
+    if (wide != 0 && !sym) return hipErrorNotSupported;
     if (wide == 1)
-        return !sym ? hipErrorNotSupported
-                    : zd ? fused_launch_np<1, true, true>(npad, one, descs, blkmap, blocks, st)
-                         : fused_launch_np<1, true, false>(npad, one, descs, blkmap, blocks, st);
+        return zd ? fused_launch_np<1, true, true>(npad, one, descs, blkmap, blocks, st)
+                  : fused_launch_np<1, true, false>(npad, one, descs, blkmap, blocks, st);
     if (wide == 2)
-        return !sym ? hipErrorNotSupported
-                    : zd ? fused_launch_np<2, true, true>(npad, one, descs, blkmap, blocks, st)
-                         : fused_launch_np<2, true, false>(npad, one, descs, blkmap, blocks, st);
+        return zd ? fused_launch_np<2, true, true>(npad, one, descs, blkmap, blocks, st)
+                  : fused_launch_np<2, true, false>(npad, one, descs, blkmap, blocks, st);
+    if (wide == 3)
+        return zd ? fused_launch_np<3, true, true>(npad, one, descs, blkmap, blocks, st)
+                  : fused_launch_np<3, true, false>(npad, one, descs, blkmap, blocks, st);
     return !sym ? fused_launch_np<0, false, false>(npad, one, descs, blkmap, blocks, st)
                 : zd ? fused_launch_np<0, true, true>(npad, one, descs, blkmap, blocks, st)
                      : fused_launch_np<0, true, false>(npad, one, descs, blkmap, blocks, st);
@@ -1001,10 +1029,10 @@ static void eval_launch_one(const InstDesc& d, const uint8_t* perms, int count, 
                             hipStream_t st)
 {
     const dim3 grid((unsigned)((count + kWaves - 1) / kWaves)), block(kWaves * kWave);
-    if constexpr (WIDE == 2 && NP > 128)
+    if constexpr (WIDE == 3 && NP > 128)
         return;  // not reached: split_supported
     else if constexpr (WIDE != 0)
-        hipLaunchKernelGGL((k_eval_wide<NP, ZD, WIDE == 2>), grid, block, 0, st, d, perms, count, goals, deltas);
+        hipLaunchKernelGGL((k_eval_wide<NP, ZD, WIDE>), grid, block, 0, st, d, perms, count, goals, deltas);
     else
         hipLaunchKernelGGL((k_eval_mfma<NP, SYM, ZD>), grid, block, 0, st, d, perms, count, goals, deltas);
 }
@@ -1030,11 +1058,15 @@ hipError_t launch_eval_mfma(const InstDesc& d, const uint8_t* perms, int count, 
     if (count <= 0) return hipSuccess;
     if (d.path == 3) {
         if (!d.sym || !split_supported(d.npad, d.split)) return hipErrorNotSupported;
-        if (d.split == 3)
-            return d.zd ? eval_launch_np<2, true, true>(d, perms, count, goals, deltas, st)
-                        : eval_launch_np<2, true, false>(d, perms, count, goals, deltas, st);
-        return d.zd ? eval_launch_np<1, true, true>(d, perms, count, goals, deltas, st)
-                    : eval_launch_np<1, true, false>(d, perms, count, goals, deltas, st);
+        switch (d.split) {
+        case 1: return d.zd ? eval_launch_np<1, true, true>(d, perms, count, goals, deltas, st)
+                            : eval_launch_np<1, true, false>(d, perms, count, goals, deltas, st);
+        case 2: return d.zd ? eval_launch_np<2, true, true>(d, perms, count, goals, deltas, st)
+                            : eval_launch_np<2, true, false>(d, perms, count, goals, deltas, st);
+        case 3: return d.zd ? eval_launch_np<3, true, true>(d, perms, count, goals, deltas, st)
+                            : eval_launch_np<3, true, false>(d, perms, count, goals, deltas, st);
+        default: return hipErrorNotSupported;
+        }
     }
     return !d.sym ? eval_launch_np<0, false, false>(d, perms, count, goals, deltas, st)
                   : d.zd ? eval_launch_np<0, true, true>(d, perms, count, goals, deltas, st)

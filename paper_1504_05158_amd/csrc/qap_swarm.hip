@@ -62,7 +62,7 @@ struct Instance {
 // symmetric, zero diagonals) its descriptors and workgroup map.
 struct FusedClass {
     int npad = 0;
-    int wide = 0;  // 0 int8, 1 byte-split (one matrix split), 2 both split
+    int wide = 0;  // 0 int8, else the byte-split pattern (1 F split, 2 D split, 3 both)
     bool sym = false, zd = false;
     int blocks = 0;
     qap::InstDesc* descs = nullptr;  // device [instances of the class]
@@ -268,7 +268,9 @@ int choose_path(const qap_instance* in, const qap_params* p, int engine, int* pa
         }
     if ((long long)n * mf * md >= (1LL << 31)) return QAP_ERR_RANGE;
     const bool fused = engine == QAP_ENGINE_FUSED && n <= 160 && p->sx_procedure == QAP_SX_SECOND_TARGET;
-    const int spl = (fs ? 1 : 0) | (ds ? 2 : 0);
+    // split pattern: bit 0 F, bit 1 D; the byte-split path asked for on data
+    // that fits int8 splits F (exactly: its high plane holds 0 or -1)
+    const int spl = (fs || !ds ? 1 : 0) | (ds ? 2 : 0);
     const bool split_ok = s && w15 && 8LL * (n + 3) * mf * md < (1LL << 31) &&
                           qap::split_supported((n + 31) / 32 * 32, spl);
     int pth;
@@ -488,7 +490,7 @@ void free_plan(StepPlan& pl)
     pl = StepPlan();
 }
 
-int fused_kind(const qap::InstDesc& d) { return d.path != 3 ? 0 : d.split == 3 ? 2 : 1; }
+int fused_kind(const qap::InstDesc& d) { return d.path != 3 ? 0 : d.split; }
 
 // Device tables of one step over the descriptors descs (entry i belongs to
 // instance owner[i]); instances whose entry is not on the fused kernel go to
@@ -702,6 +704,9 @@ int apply_plan(qap_swarm* h, const PlanCfg& c)
         h->migr_descs = static_cast<qap::InstDesc*>(q);
         if (e != hipSuccess) return dev_err(nullptr, e);
     }
+    // chain 0 runs on the handle's stream, the others on streams of their own
+    // (a process's streams share the runtime's hardware queues, 4 by default:
+    // two chains on one queue run one after the other)
     if (h->gstream.empty()) h->gstream.push_back(h->stream);
     while ((int)h->gstream.size() < G) {
         hipStream_t st;
@@ -1066,9 +1071,21 @@ int impl_step(qap_swarm* h, int32_t iterations)
     const int G = (int)h->plans.size();
     hipError_t e = hipSuccess;
     // the groups start after the work already on the handle's stream ...
+    auto fork = [&]() {
+        hipError_t r = hipEventRecord(h->gevent[0], h->stream);
+        for (int j = 1; j < G && r == hipSuccess; ++j) r = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
+        return r;
+    };
+    auto join = [&]() {
+        hipError_t r = hipSuccess;
+        for (int j = 1; j < G && r == hipSuccess; ++j) {
+            r = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
+            if (r == hipSuccess) r = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
+        }
+        return r;
+    };
     if (G > 1) {
-        e = hipEventRecord(h->gevent[0], h->stream);
-        for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
+        e = fork();
         if (e != hipSuccess) return dev_err(h, e);
     }
     for (int it = 0; it < iterations;) {
@@ -1101,10 +1118,7 @@ int impl_step(qap_swarm* h, int32_t iterations)
         // host synchronisation)
         const bool mig = !multi && migration_due(h, it, 1);
         if (mig || record) {
-            for (int j = 1; j < G && e == hipSuccess; ++j) {
-                e = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
-                if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
-            }
+            if (G > 1) e = join();
             if (e == hipSuccess && mig) e = qap::launch_migrate(h->migr_descs, (int)h->migr.size(), h->stream);
             for (size_t k = 0; k < h->inst.size() && e == hipSuccess && record; ++k) {
                 const Instance& I = h->inst[k];
@@ -1113,8 +1127,7 @@ int impl_step(qap_swarm* h, int32_t iterations)
                                             I.hist_lo, I.hist_hi, I.hist_cap, I.ring_t, I.ring_q, I.ring_h,
                                             h->stream);
             }
-            if (e == hipSuccess) e = hipEventRecord(h->gevent[0], h->stream);
-            for (int j = 1; j < G && e == hipSuccess; ++j) e = hipStreamWaitEvent(h->gstream[(size_t)j], h->gevent[0], 0);
+            if (e == hipSuccess && G > 1) e = fork();
             if (e != hipSuccess) return dev_err(h, e);
         }
         it += chunk;
@@ -1124,10 +1137,7 @@ int impl_step(qap_swarm* h, int32_t iterations)
         I.t += iterations;
     }
     // ... and the handle's stream continues after all of them
-    for (int j = 1; j < G && e == hipSuccess; ++j) {
-        e = hipEventRecord(h->gevent[(size_t)j], h->gstream[(size_t)j]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->gevent[(size_t)j], 0);
-    }
+    if (G > 1) e = join();
     return dev_err(h, e);
 }
 
@@ -1661,6 +1671,7 @@ int reset_state(qap_swarm* h)
 }
 
 constexpr int kTuneWarmup = 10;
+constexpr size_t kTuneFinalists = 4;  // plans timed again by the tuner
 
 // Time every candidate plan on the handle's own work (from iteration 0, a
 // warm-up, then `trial` iterations between events on the handle's stream),
@@ -1690,28 +1701,43 @@ int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
         if (e0) (void)hipEventDestroy(e0);
         return QAP_ERR_DEVICE;
     }
+    // every plan is timed on the same iterations: from iteration 0, the first
+    // kTuneWarmup untimed (graph capture, the fast first iterations)
+    auto time_plan = [&](const PlanCfg& c, int iters, float* ms) {
+        int r = apply_plan(h, c);
+        if (r == QAP_OK) r = reset_state(h);
+        if (r == QAP_OK) r = impl_step(h, kTuneWarmup);
+        hipError_t e = r == QAP_OK ? hipEventRecord(e0, h->stream) : hipSuccess;
+        if (r == QAP_OK && e == hipSuccess) r = impl_step(h, iters);
+        if (r == QAP_OK && e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (r == QAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        *ms = 0.0f;
+        if (r == QAP_OK && e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+        if (r == QAP_OK && e != hipSuccess) r = dev_err(h, e);
+        *ms /= (float)iters;
+        return r;
+    };
+    // round 1: every candidate; round 2: the fastest few again, on twice the
+    // iterations, in reverse order (a plan timed first is not favoured twice)
+    std::vector<std::pair<float, size_t>> first;
+    int rc = QAP_OK;
+    for (size_t i = 0; i < cands.size() && rc == QAP_OK; ++i) {
+        float ms = 0.0f;
+        rc = time_plan(cands[i], trial, &ms);
+        first.emplace_back(ms, i);
+    }
     PlanCfg best = h->cfg;
     float best_ms = 0.0f;
-    int rc = QAP_OK;
-    for (const PlanCfg& c : cands) {
-        // every plan is timed on the same iterations: from iteration 0, the
-        // first kTuneWarmup untimed (graph capture, the fast first iterations)
-        rc = apply_plan(h, c);
-        if (rc == QAP_OK) rc = reset_state(h);
-        if (rc != QAP_OK) break;
-        rc = impl_step(h, kTuneWarmup);
-        hipError_t e = rc == QAP_OK ? hipEventRecord(e0, h->stream) : hipSuccess;
-        if (rc == QAP_OK && e == hipSuccess) rc = impl_step(h, trial);
-        if (rc == QAP_OK && e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (rc == QAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.0f;
-        if (rc == QAP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rc == QAP_OK && e != hipSuccess) rc = dev_err(h, e);
-        if (rc != QAP_OK) break;
-        ms /= (float)trial;
-        if (best_ms == 0.0f || ms < best_ms) {
-            best = c;
-            best_ms = ms;
+    if (rc == QAP_OK) {
+        std::stable_sort(first.begin(), first.end());
+        const size_t keep = std::min<size_t>(kTuneFinalists, first.size());
+        for (size_t j = keep; j-- > 0 && rc == QAP_OK;) {
+            float ms = 0.0f;
+            rc = time_plan(cands[first[j].second], 2 * trial, &ms);
+            if (rc == QAP_OK && (best_ms == 0.0f || ms < best_ms)) {
+                best = cands[first[j].second];
+                best_ms = ms;
+            }
         }
     }
     (void)hipEventDestroy(e0);
