@@ -52,7 +52,9 @@ def algorithmic_bytes(stage: str, n: int) -> int:
     return 0
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fused_n128x10k_traffic.md")
+def traffic_file(workload: str) -> str:
+    """The committed HBM-traffic summary of the fused kernel on a workload."""
+    return os.path.join(ROOT, "profiles", "fused_%s_traffic.md" % workload)
 KERNEL_SOURCES = ["common.hpp", "philox.hpp", "dword.hpp", "second_target.hpp", "kernels_fused.hip"]
 
 
@@ -65,13 +67,13 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(workload: str):
     """HBM bytes per step of the fused kernel (all its launches of one
-    iteration) from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
-    each scaled by the same counter on a copy of known size), or None if absent
-    or taken on other kernel sources."""
+    iteration) from the committed counter summary of the workload (FETCH_SIZE +
+    WRITE_SIZE, each scaled by the same counter on a copy of known size), or
+    None if absent or taken on other kernel sources."""
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(traffic_file(workload)).read()
     except OSError:
         return None
     m = re.search(r"source hash:\s*`?([0-9a-f]+)", text)
@@ -192,7 +194,10 @@ def run_gpu(args, engine: str):
     # second run from the same seed replays exactly the timed iterations (events
     # stay out of the timed run, where they would add a few percent)
     if args.no_profile_pass:
-        stage_ms, iters = {"fused": region_ms * args.steps * groups}, args.steps
+        # the fused engine's iteration is its fused kernel (and the small bests
+        # kernels); the per-stage engine's is reported as a whole
+        key = "fused" if engine == "fused" else "iteration"
+        stage_ms, iters = {key: region_ms * args.steps * groups}, args.steps
     else:
         sw = make()
         sw.step(args.warmup)
@@ -209,15 +214,15 @@ def run_gpu(args, engine: str):
         roof = dict(bound="alu", achieved=round(achieved, 3), peak=VALU_INT_PEAK_TOPS, unit="TOP/s",
                     frac=round(achieved / VALU_INT_PEAK_TOPS, 4), traffic=None)
     else:
-        bps = workload_bytes(insts, dom)  # per step, over the `launches` concurrent launches
+        bps = workload_bytes(insts, "fused" if dom == "iteration" else dom)  # per step, over the `launches` launches
         if launches > 1:
             # concurrent launches overlap: the aggregate rate is the step's bytes over the
             # event-timed region per step (which also holds the small bests kernels)
             achieved = bps / (region_ms * 1e-3) / 1e9
         else:
             achieved = bps / (avg_ms * 1e-3) / 1e9
-        headline = args.workload == WORKLOAD["name"]
-        traffic = measured_traffic() if (dom == "fused" and engine == "fused" and headline) else None
+        traffic = (measured_traffic(args.workload)
+                   if (dom == "fused" and engine == "fused" and args.local_search is None) else None)
         roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4),
                     traffic=None if traffic is None else round(traffic / 1e9, 4))
@@ -233,33 +238,49 @@ def run_gpu(args, engine: str):
                 groups=groups, instances=len(insts), plan=plan)
 
 
-def cpu_baseline(target_s: float = 15.0, max_steps: int = 50, threads: int = 16, swarms: int | None = None):
-    """The oracle, as it stands, stepping the headline workload (or its first
-    `swarms` swarms: the same instance and per-particle work) until about
-    target_s seconds have passed, on `threads` OpenMP threads (at most the
-    host's cores)."""
-    import oracle as orc
-    import qap_inputs as gen
+ORACLE_KEYS = ("c1", "c2", "c3", "vmax", "norm", "depth", "local_search", "migration", "migration_factor",
+               "migration_period", "seed")
 
-    n = WORKLOAD["n"]
-    F, D = gen.uniform_instance(n, 0, 127, WORKLOAD["seed_inst"])
+
+def cpu_baseline(workload: str, target_s: float = 15.0, max_steps: int = 2000, threads: int = 16,
+                 swarms: int | None = None, per: int | None = None):
+    """The oracle, as it stands, stepping the workload (or a sample of it: at
+    most `swarms` swarms of each instance, `per` particles each -- the same
+    instances and per-particle work) until about target_s seconds have passed,
+    on `threads` OpenMP threads (at most the host's cores)."""
+    import oracle as orc
+
+    insts = workload_setup(workload)
     orc.set_threads(max(1, min(threads, os.cpu_count() or 1)))
     used = orc.get_threads()
-    S, per = swarms or WORKLOAD["num_swarms"], WORKLOAD["particles_per_swarm"]
-    sw = orc.OracleSwarm(F, D, num_swarms=S, particles_per_swarm=per, **RUN)
+    sws = []
+    for F, D, p in insts:
+        S = p["num_swarms"] if swarms is None else min(swarms, p["num_swarms"])
+        Sp = p["particles_per_swarm"] if per is None else min(per, p["particles_per_swarm"])
+        sws.append(orc.OracleSwarm(F, D, num_swarms=S, particles_per_swarm=Sp,
+                                   **{k: p[k] for k in ORACLE_KEYS if k in p}))
+    parts = sum(sw.P for sw in sws)
     steps = 0
     t0 = time.perf_counter()
     while steps < max_steps:
-        sw.step(1)
+        for sw in sws:
+            sw.step(1)
         steps += 1
         if time.perf_counter() - t0 >= target_s:
             break
     secs = time.perf_counter() - t0
-    what = "the whole workload" if swarms is None else "the first %d of its 200 swarms" % S
-    return dict(value=round(S * per * steps / secs, 2), unit="particle-iterations/s", cores=used,
+    total = sum(p["num_swarms"] * p["particles_per_swarm"] for _, _, p in insts)
+    if len(insts) == 1:
+        F, _, p = insts[0]
+        what = ("the whole workload" if parts == total else "the first %d of its %d swarms" % (sws[0].m, p["num_swarms"]))
+        what += " (%d swarms x %d particles, n=%d)" % (sws[0].m, sws[0].S, F.shape[0])
+    else:
+        what = ("the whole workload" if parts == total else "every instance with %d swarm(s) x %d particles"
+                % (sws[0].m, sws[0].S)) + " (%d instances, %d particles)" % (len(insts), parts)
+    return dict(value=round(parts * steps / secs, 2), unit="particle-iterations/s", cores=used,
                 kind="oracle",
-                sample="%s (%d swarms x %d particles, n=%d), iterations 1-%d, %d OpenMP thread%s, %.1f s"
-                       % (what, S, per, n, steps, used, "" if used == 1 else "s", secs))
+                sample="%s, iterations 1-%d, %d OpenMP thread%s, %.1f s"
+                       % (what, steps, used, "" if used == 1 else "s", secs))
 
 
 def trace_span(path: str, args) -> dict:
@@ -374,10 +395,14 @@ def main():
     if other is not None:
         line["compare"] = {("plain" if args.engine == "fused" else "fused"):
                            (round(other["value"], 1) if "value" in other else other)}
-    if not args.no_cpu_baseline and headline:
-        line["cpu_baseline"] = cpu_baseline()
-        # one core, on the first 8 swarms (400 particles: an iteration takes seconds)
-        line["cpu_baseline"]["one_core"] = cpu_baseline(target_s=10.0, threads=1, swarms=8)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.workload)
+        # one core on a sample whose iteration takes about a second or two: the
+        # headline's first 8 swarms (400 particles), one swarm of the other
+        # single-instance workloads, 8 particles of every instance of the batch
+        sample = (dict(swarms=8) if headline else dict(swarms=1, per=8) if args.workload == MIXED["name"]
+                  else dict(swarms=1))
+        line["cpu_baseline"]["one_core"] = cpu_baseline(args.workload, target_s=10.0, threads=1, **sample)
     print(json.dumps(line), flush=True)
 
 
