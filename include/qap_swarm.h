@@ -96,8 +96,8 @@ typedef struct {
  *    per-stage kernels, whatever the engine).
  *  stream_groups: 0 = automatic (swarms on the fused kernel are stepped as up
  *    to 3 concurrent groups of swarms, see qap_swarm_step and qap_plan), or
- *    1-4 to set the number of groups of this instance (results are the same
- *    for every choice). */
+ *    1-QAP_MAX_CHAINS to set the number of groups of this instance (results
+ *    are the same for every choice). */
 typedef struct {
     int32_t num_swarms;
     int32_t particles_per_swarm;
@@ -204,9 +204,10 @@ int qap_swarm_step(qap_swarm* h, int32_t iterations);
  * else on 3 chains (or the instances' stream_groups), split by swarms, graphs
  * of 8 iterations.  qap_swarm_set_plan may be called between any two steps
  * (QAP_ERR_INVALID_ARG for a plan outside the ranges above).
- * qap_swarm_tune times every plan (chains 1..4 x split x {eager, 1, 8}
- * iterations per graph; the instance and class splits only for several
- * instances) on the handle's own work, each from iteration 0 -- 10
+ * qap_swarm_tune times every plan (chains 1..c x split x {eager, 1, 8}
+ * iterations per graph, where c = GPU_MAX_HW_QUEUES - 1 (4 queues when the
+ * variable is unset), at most QAP_MAX_CHAINS; the instance and class splits
+ * only for several instances) on the handle's own work, each from iteration 0 -- 10
  * iterations of warm-up, then trial_iterations (1..4096) between events --
  * then times the 4 fastest again on 2 x trial_iterations, keeps the fastest
  * of that round, and returns the handle to iteration 0 (the state init made,

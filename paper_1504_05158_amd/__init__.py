@@ -27,6 +27,8 @@ QAP_SV_RAW, QAP_SV_NORM = 0, 1
 QAP_INDEPENDENT, QAP_MIGRATION = 0, 1
 QAP_PATH_AUTO, QAP_PATH_INT8_MFMA, QAP_PATH_INT32, QAP_PATH_SPLIT_MFMA = 0, 1, 2, 3
 QAP_ENGINE_FUSED, QAP_ENGINE_PLAIN = 0, 1
+QAP_MAX_CHAINS = 4
+QAP_SPLIT_SWARMS, QAP_SPLIT_INSTANCES, QAP_SPLIT_CLASSES = 0, 1, 2
 
 EXPORTS = ["qap_swarm_init", "qap_swarm_init_batch", "qap_swarm_step", "qap_swarm_sync", "qap_swarm_best",
            "qap_swarm_swarm_bests", "qap_swarm_get_state", "qap_swarm_set_state", "qap_swarm_eval",

@@ -1687,8 +1687,13 @@ int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
         if (I.t != 0 || I.stepped || I.hist_cap > 0) return QAP_ERR_INVALID_ARG;  // from iteration 0, not recording
     std::vector<PlanCfg> cands;
     const bool several = h->inst.size() > 1;
+    // chains beyond the runtime's hardware queues less one (the handle's
+    // stream takes one) would share a queue and run one after the other
+    const char* hwq = std::getenv("GPU_MAX_HW_QUEUES");
+    const int queues = hwq && std::atoi(hwq) > 0 ? std::atoi(hwq) : 4;
+    const int max_chains = std::max(1, std::min(kMaxChains, queues - 1));
     for (int split = 0; split <= (several ? 2 : 0); ++split)
-        for (int chains = 1; chains <= kMaxChains; ++chains)
+        for (int chains = 1; chains <= max_chains; ++chains)
             for (int ipg : {0, 1, kItersPerGraph}) {
                 PlanCfg c;
                 c.chains = chains;

@@ -36,6 +36,15 @@ def test_library_exports_every_declared_symbol(L):
     assert sorted(q.EXPORTS) == declared()
 
 
+def test_binding_constants_match_the_header():
+    import paper_1504_05158_amd as q
+    src = open(HEADER).read()
+    for name in ("QAP_MAX_CHAINS", "QAP_SPLIT_SWARMS", "QAP_SPLIT_INSTANCES", "QAP_SPLIT_CLASSES",
+                 "QAP_PATH_SPLIT_MFMA", "QAP_ENGINE_PLAIN"):
+        m = re.search(r"\b%s\s*=\s*(\d+)" % name, src)
+        assert m and int(m.group(1)) == getattr(q, name), name
+
+
 def test_strerror_and_null_safety(L):
     assert L.qap_swarm_strerror(0) == b"ok"
     assert b"range" in L.qap_swarm_strerror(-2)

@@ -121,7 +121,7 @@ def test_tune_returns_to_the_initial_state_and_caches_its_choice(q, tmp_path):
     with pytest.raises(q.QapError) as e:
         bad = make(q, cs)
         try:
-            bad.set_plan(5, 0, 8)
+            bad.set_plan(q.QAP_MAX_CHAINS + 1, 0, 8)
         finally:
             bad.close()
     assert e.value.code == q.QAP_ERR_INVALID_ARG
