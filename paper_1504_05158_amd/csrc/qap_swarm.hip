@@ -1722,7 +1722,7 @@ int impl_tune(qap_swarm* h, int32_t trial, qap_plan* chosen)
         *ms /= (float)iters;
         return r;
     };
-    // round 1: every candidate; round 2: the fastest few again, on twice the
+    // a first pass over every candidate, then a second over the fastest few, on twice the
     // iterations, in reverse order (a plan timed first is not favoured twice)
     std::vector<std::pair<float, size_t>> first;
     int rc = QAP_OK;
