@@ -192,11 +192,19 @@ __device__ void goal_delta_mfma(int n, const int8_t* sF, const int8_t* sD, const
             // The minimum is kept as one int, delta * 16 + i (|delta| < 2^26 for int8
             // entries and n <= 160): the smallest delta, then the first element.
             int tkey = INT_MAX;
+            // the row info of the next element is read while this one is
+            // evaluated: the D read indexed by p_x then waits for one LDS round
+            // trip per element instead of two
+            RowInfo rxn = rxb[0];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int xo = 8 * (i >> 2) + (i & 3);
-                if (a == b && 32 * a + 4 * h + xo >= y) continue;  // diagonal tiles: x < y only
-                const RowInfo rx = rxb[xo];
+                const RowInfo rx = rxn;
+                if (i + 1 < 16) rxn = rxb[8 * ((i + 1) >> 2) + ((i + 1) & 3)];
+                if (a == b && 32 * a + 4 * h + xo >= y) {  // diagonal tiles: x < y only
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
+                }
                 const int fxy = fxb[xo * LS];
                 const int dxy = sD[__umul24(rx.p, LSD) + cy.p];  // 24-bit multiply: p < 256
                 int del;
@@ -828,13 +836,25 @@ __device__ void goal_delta_wide(int n, const int8_t* pl, const uint8_t* sp, uint
             const RowW cy = sri[y];
             const int py = sp[y];
             int tmin = INT_MAX, ti = 0;
+            // the next element's row info and p_x are read while this one is
+            // evaluated (one LDS round trip per element instead of two)
+            RowW rxn = sri[32 * a + 4 * h];
+            int pxn = sp[32 * a + 4 * h];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int xo = 8 * (i >> 2) + (i & 3);
                 const int x = 32 * a + 4 * h + xo;
-                if (a == b && x >= y) continue;  // diagonal tiles: x < y only
-                const RowW rx = sri[x];
-                const int px = sp[x];
+                const RowW rx = rxn;
+                const int px = pxn;
+                if (i + 1 < 16) {
+                    const int xn = 32 * a + 4 * h + 8 * ((i + 1) >> 2) + ((i + 1) & 3);
+                    rxn = sri[xn];
+                    pxn = sp[xn];
+                }
+                if (a == b && x >= y) {  // diagonal tiles: x < y only
+                    __builtin_amdgcn_sched_barrier(0);
+                    continue;
+                }
                 const int fxy = wide_val<PS, fs>(fl, x * LS + y);
                 const int dxy = wide_val<PS, ds>(dl, __umul24(px, LS) + py);
                 const int base = 2 * acc[i] - rx.da - cy.da;
