@@ -55,7 +55,7 @@ def algorithmic_bytes(stage: str, n: int) -> int:
 def traffic_file(workload: str) -> str:
     """The committed HBM-traffic summary of the fused kernel on a workload."""
     return os.path.join(ROOT, "profiles", "fused_%s_traffic.md" % workload)
-KERNEL_SOURCES = ["common.hpp", "philox.hpp", "dword.hpp", "second_target.hpp", "kernels_fused.hip"]
+KERNEL_SOURCES = ["common.hpp", "philox.hpp", "dword.hpp", "second_target.hpp", "kernels.hpp", "kernels_fused.hip"]
 
 
 def kernel_hash() -> str:
