@@ -125,3 +125,23 @@ def test_tune_returns_to_the_initial_state_and_caches_its_choice(q, tmp_path):
         finally:
             bad.close()
     assert e.value.code == q.QAP_ERR_INVALID_ARG
+
+
+def test_tune_keeps_chains_within_the_hardware_queues(q):
+    """With GPU_MAX_HW_QUEUES = 2 only one chain fits beside the handle's own
+    stream's queue: the tuner then times single-chain plans only."""
+    cs = cases()
+    announce("tune, queue bound")
+    old = os.environ.get("GPU_MAX_HW_QUEUES")
+    os.environ["GPU_MAX_HW_QUEUES"] = "2"
+    try:
+        h = make(q, cs)
+        chosen = h.tune(4)
+        assert chosen["stream_chains"] == 1
+        assert h.plan()["stream_chains"] == 1
+        h.close()
+    finally:
+        if old is None:
+            os.environ.pop("GPU_MAX_HW_QUEUES", None)
+        else:
+            os.environ["GPU_MAX_HW_QUEUES"] = old
