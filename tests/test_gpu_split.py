@@ -134,8 +134,9 @@ def test_split_one_step_parity(q, orc, name, mk, split, ls):
 
 
 def test_split_requested_on_int8_data(q, orc):
-    """delta_path='split' on data that fits int8: no plane is split and the
-    kernel runs on the low planes alone (negative entries included)."""
+    """delta_path='split' on data that fits int8: F is split all the same
+    (its high plane holds 0 or -1, negative entries included) and the result
+    is exact."""
     F, D = gen.general_instance(30, -128, 127, 9)
     F = (F + F.T) // 2
     D = (D + D.T) // 2
