@@ -8,13 +8,6 @@ namespace qap {
 constexpr int kWave = 64;
 constexpr int kMaxN = 256;
 
-// Row stride (in floats) of a particle's n x n velocity matrix: rows padded to
-// a multiple of 32 floats (128 bytes), so that every row starts a cache line
-// and the column passes of a row never share a line (with unpadded rows the
-// line holding the end of one row and the start of the next was fetched by
-// one pass and again, after eviction, by the other).
-__host__ __device__ constexpr int vld(int n) { return (n + 31) & ~31; }
-
 // Best-ever record of an instance (device memory).
 struct BestRec {
     long long goal;
@@ -64,7 +57,7 @@ struct InstDesc {
     // unnormalised S_v output and Vinv the reciprocal column norm (1 for raw
     // S_v).  Applying the scale on read gives the same binary32 value as
     // storing the normalised matrix, and lets the velocity pass stream.
-    float* V[2];            // [P][n][vld(n)] U, row = location, column = facility
+    float* V[2];            // [P][n][n] U, row = location, column = facility
     float* Vinv[2];         // [P][n]    column scale
     uint8_t* X[2];          // [P][n]   p[i] = location of facility i
     uint8_t* PL;            // [P][n]

@@ -291,7 +291,7 @@ __device__ __forceinline__ float attract_cell(float c1, float x, DW o, float vma
 // row offsets go to the scalar offset, the lane's column to the vector one.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t matrix_rsrc(const float* p, int n)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, 4 * n * vld(n), 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, 4 * n * n, 0x00020000);
 }
 
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
@@ -352,94 +352,90 @@ __device__ __forceinline__ void top2(float x, int u, float& m1, int& u1, float& 
     m1 = le ? m1 : x;
 }
 
-// Column c of the velocity pass over one particle's V(t) (rp) into V(t+1)
-// before the column norm (rq): returns the sum of |.| rounded once from a
-// double word (each batch of 32 rows summed in binary32 as four interleaved
-// partial sums of 8, then added to the double word with the attraction-cell
-// corrections, without loss: a relative error of at most 9 units of 2^-24 at
-// any n, where one binary32 running sum could reach n - 1), and the column's
-// largest V(t) value m1
-// (first row r1), its runner-up m2, and vx = V(t) at the X row.  Rows are
-// loaded in batches so that many loads are in flight; the attraction cells of
-// a batch are read with it and fixed right after it.
+// The state of one column in the velocity pass: its attraction rows and
+// which of them differ (packed: X row, P^L row, P^G row in bytes 0-2; bit 24
+// P^L row != X row, bit 25 P^G row != X row, bit 26 P^L row == P^G row), the
+// scale of V(t), the sum of |.| of the new column so far (a double word), the
+// largest V(t) value m1 (first row r1), its runner-up m2, and vx = V(t) at the
+// X row.
+struct ColStream {
+    uint32_t rows;
+    float sc;
+    DW sum;
+    float m1, m2, vx;
+    int r1;
+};
+
+// The attraction rows and terms of a column (velocity equation) from its
+// packed rows and the particle's s2 = c2 r2, s3 = c3 r3 and s23 = s2 + s3:
+// ox = -(s2 if the P^L row differs) - (s3 if the P^G row differs),
+// ol = s2 (+ s3 if the P^G row is the P^L row).
+__device__ __forceinline__ Attract unpack_attract(uint32_t rows, DW s2, DW s3, DW s23)
+{
+    Attract at;
+    at.xr = (int)(rows & 0xffu);
+    at.lr = (int)((rows >> 8) & 0xffu);
+    at.gr = (int)((rows >> 16) & 0xffu);
+    const bool nl = (rows >> 24) & 1u, ng = (rows >> 25) & 1u;
+    const DW o = nl && ng ? s23 : nl ? s2 : ng ? s3 : DW{0.0f, 0.0f};
+    at.ox = dw_neg(o);
+    at.ol = (rows >> 26) & 1u ? s23 : s2;
+    return at;
+}
+
+// Rows [r0, min(r0 + B, n)) of the column at byte offset col of the velocity
+// pass over one particle's V(t) (rp) into V(t+1) before the column norm (rq).
+// The batch is summed in binary32 as four interleaved partial sums of B / 4,
+// then added to the column's double word with the attraction-cell
+// corrections, without loss: the column sum, rounded once at the end, has a
+// relative error of at most 9 units of 2^-24 at any n (B = 32; 5 at B = 16),
+// where one binary32 running sum could reach n - 1.  The B loads of a batch
+// are issued together, and the attraction cells of the batch are read with it
+// and fixed right after it.
+// TAIL: the last rows, fewer than B (row indices clamped to the matrix, the
+// rows past n skipped by uniform branches).
 // FOLDX: the X-row cell by a select (at npad >= 128, where it costs no
 // registers), else re-stored like the others.
-template <bool FOLDX>
-__device__ __forceinline__ float stream_column(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int c, int n,
-                                               float sc, float c1, DW s3, float vmax, const Attract& at,
-                                               float& m1, int& r1, float& m2, float& vx)
+template <int B, bool FOLDX, bool TAIL>
+__device__ __forceinline__ void stream_batch(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, uint32_t col,
+                                             uint32_t rowb, int n, int r0, float c1, DW s2, DW s3, DW s23,
+                                             float vmax, ColStream& cs)
 {
-    constexpr int B = 32;
-    const uint32_t col = 4u * (uint32_t)c, rowb = 4u * (uint32_t)vld(n);
-    DW sum{0.0f, 0.0f};
-    int r0 = 0;
-    for (; r0 + B <= n; r0 += B) {
-        float v[B];
+    const Attract at = unpack_attract(cs.rows, s2, s3, s23);
+    const int hi = TAIL ? n : r0 + B;
+    float v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)(r0 + u) * rowb);
-        // attraction rows of this batch (row r0 stands in for absent ones: same lines)
-        const int hi = r0 + B;
-        const float ex = bload(rp, col + __umul24(at.xr >= r0 && at.xr < hi ? at.xr : r0, rowb), 0u);
-        const float el = bload(rp, col + __umul24(at.lr >= r0 && at.lr < hi ? at.lr : r0, rowb), 0u);
-        const float eg = bload(rp, col + __umul24(at.gr >= r0 && at.gr < hi ? at.gr : r0, rowb), 0u);
-        // the X-row cell (one in every column) takes its attraction value by a
-        // select before the row's single store; the P^L and P^G cells (which
-        // equal the X row or each other more and more often late in a run) are
-        // re-stored after the batch: a second store to a line just written
-        // leaves L2 as a partial write of its own, and three selects per row
-        // would cost the registers of a wave per SIMD
-        const float tx = attract_cell(c1, __fmul_rn(ex, sc), at.ox, vmax);
-        const int dx = FOLDX ? at.xr - r0 : -1;
-        if (FOLDX && dx >= 0 && dx < B) vx = __fmul_rn(ex, sc);
-        const float mb = m1;
-        int u1 = 0;
-        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // rows u = 0, 1, 2, 3 mod 4
+    for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)(TAIL ? min(r0 + u, n - 1) : r0 + u) * rowb);
+    // attraction rows of this batch (row r0 stands in for absent ones: same lines)
+    const float ex = bload(rp, col + __umul24(at.xr >= r0 && at.xr < hi ? at.xr : r0, rowb), 0u);
+    const float el = bload(rp, col + __umul24(at.lr >= r0 && at.lr < hi ? at.lr : r0, rowb), 0u);
+    const float eg = bload(rp, col + __umul24(at.gr >= r0 && at.gr < hi ? at.gr : r0, rowb), 0u);
+    // the X-row cell (one in every column) takes its attraction value by a
+    // select before the row's single store; the P^L and P^G cells (which
+    // equal the X row or each other more and more often late in a run) are
+    // re-stored after the batch: a second store to a line just written
+    // leaves L2 as a partial write of its own, and three selects per row
+    // would cost the registers of a wave per SIMD
+    const float tx = attract_cell(c1, __fmul_rn(ex, cs.sc), at.ox, vmax);
+    const int dx = FOLDX ? at.xr - r0 : -1;
+    if (FOLDX && dx >= 0 && dx < B) cs.vx = __fmul_rn(ex, cs.sc);
+    const float mb = cs.m1;
+    int u1 = 0;
+    float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // rows u = 0, 1, 2, 3 mod 4
 #pragma unroll
-        for (int u = 0; u < B; ++u) {
-            const float x = __fmul_rn(v[u], sc);
-            top2(x, u, m1, u1, m2);
+    for (int u = 0; u < B; ++u) {
+        if (!TAIL || u < n - r0) {
+            const float x = __fmul_rn(v[u], cs.sc);
+            top2(x, u, cs.m1, u1, cs.m2);
             float t = clampv(__fmul_rn(c1, x), vmax);
             if constexpr (FOLDX) t = u == dx ? tx : t;
             bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
             part[u & 3] = __fadd_rn(part[u & 3], fabsf(t));
         }
-        sum = dw_add_f(sum, __fadd_rn(__fadd_rn(part[0], part[1]), __fadd_rn(part[2], part[3])));
-        r1 = m1 != mb ? r0 + u1 : r1;  // the maximum rose in this batch
-        fix_cells<!FOLDX>(rq, col, rowb, r0, hi, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
     }
-    if (r0 < n) {
-        // the last rows, fewer than a batch, as one more batch: all loads are
-        // issued together (row indices clamped to the matrix), the rows past
-        // n skipped by uniform branches
-        const int valid = n - r0;
-        float v[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = bload(rp, col, (uint32_t)min(r0 + u, n - 1) * rowb);
-        const float ex = bload(rp, col + __umul24(at.xr >= r0 ? at.xr : r0, rowb), 0u);
-        const float el = bload(rp, col + __umul24(at.lr >= r0 ? at.lr : r0, rowb), 0u);
-        const float eg = bload(rp, col + __umul24(at.gr >= r0 ? at.gr : r0, rowb), 0u);
-        const float tx = attract_cell(c1, __fmul_rn(ex, sc), at.ox, vmax);
-        const int dx = FOLDX ? at.xr - r0 : -1;
-        if (FOLDX && dx >= 0) vx = __fmul_rn(ex, sc);
-        const float mb = m1;
-        int u1 = 0;
-        float part[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-            if (u < valid) {
-                const float x = __fmul_rn(v[u], sc);
-                top2(x, u, m1, u1, m2);
-                float t = clampv(__fmul_rn(c1, x), vmax);
-                if constexpr (FOLDX) t = u == dx ? tx : t;
-                bstore(rq, col, (uint32_t)(r0 + u) * rowb, t);
-                part[u & 3] = __fadd_rn(part[u & 3], fabsf(t));
-            }
-        }
-        sum = dw_add_f(sum, __fadd_rn(__fadd_rn(part[0], part[1]), __fadd_rn(part[2], part[3])));
-        r1 = m1 != mb ? r0 + u1 : r1;
-        fix_cells<!FOLDX>(rq, col, rowb, r0, n, at, ex, el, eg, sc, c1, s3, vmax, sum, vx);
-    }
-    return __fadd_rn(sum.hi, sum.lo);
+    cs.sum = dw_add_f(cs.sum, __fadd_rn(__fadd_rn(part[0], part[1]), __fadd_rn(part[2], part[3])));
+    cs.r1 = cs.m1 != mb ? r0 + u1 : cs.r1;  // the maximum rose in this batch
+    fix_cells<!FOLDX>(rq, col, rowb, r0, hi, at, ex, el, eg, cs.sc, c1, s3, vmax, cs.sum, cs.vx);
 }
 
 }  // namespace
@@ -458,8 +454,8 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
     const int cur = tprev & 1;
     const int gs = k / d.S;  // swarm within this descriptor; g: within the instance
     const uint32_t g = (uint32_t)(gs + d.swarm_base), s = (uint32_t)(k % d.S);
-    global_t<const float>* Vp = gl(buf(d.V, cur)) + (size_t)k * n * vld(n);
-    float* Vq = buf(d.V, cur ^ 1) + (size_t)k * n * vld(n);  // buffer stores
+    global_t<const float>* Vp = gl(buf(d.V, cur)) + (size_t)k * n * n;
+    float* Vq = buf(d.V, cur ^ 1) + (size_t)k * n * n;  // buffer stores
     global_t<const uint8_t>* Xk = gl(buf(d.X, cur)) + (size_t)k * n;
     const Philox4 rb = philox4x32_10(0u, tau, s, g, (uint32_t)d.seed, (uint32_t)(d.seed >> 32));
     // c2 r2, c3 r3 (exact double words) and their sum: the attraction terms
@@ -477,25 +473,71 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
 #pragma unroll
     for (int j = 0; j < CPL; ++j)
         if (l + kWave * j < n) st.rowbits |= 1u << j;
+    // The lane's columns l, l + 64, ...  Rows are n floats, unpadded, so the
+    // line holding the end of one row and the start of the next is shared by
+    // the lane's columns: with several columns per lane the pass runs over
+    // batches of 16 rows, each batch through every column before the next, so
+    // that such a line is fetched once (a pass per column over the whole
+    // matrix fetched it twice, the second time after eviction).  16-row
+    // batches keep two columns' state within the registers of one 32-row
+    // batch.  With one column per lane a row is one load: batches of 32.
+    ColStream cs[CPL];
+#pragma unroll
+    for (int kk = 0; kk < CPL; ++kk) {
+        const int c = l + kWave * kk;
+        ColStream& z = cs[kk];
+        z.m1 = -INFINITY; z.m2 = -INFINITY; z.vx = 0.0f; z.r1 = -1;
+        z.sum = DW{0.0f, 0.0f};
+        z.rows = 0u;
+        z.sc = 1.0f;
+        if (c < n) {
+            const uint32_t xr = Xk[c], lr = gl(d.PL)[(size_t)k * n + c], gr = gl(d.PG)[(size_t)gs * n + c];
+            z.rows = xr | lr << 8 | gr << 16 | (uint32_t)(lr != xr) << 24 | (uint32_t)(gr != xr) << 25 |
+                     (uint32_t)(lr == gr) << 26;
+            z.sc = Sp[c];
+        }
+    }
+    constexpr bool FOLDX = NP >= 128;
+    const uint32_t rowb = 4u * (uint32_t)n;
+    if constexpr (CPL == 1) {
+        if (l < n) {
+            int r0 = 0;
+            for (; r0 + 32 <= n; r0 += 32)
+                stream_batch<32, FOLDX, false>(rp, rq, 4u * l, rowb, n, r0, c1, s2, s3, s23, vmax, cs[0]);
+            if (r0 < n) stream_batch<32, FOLDX, true>(rp, rq, 4u * l, rowb, n, r0, c1, s2, s3, s23, vmax, cs[0]);
+        }
+    } else {
+        constexpr int RB = 16;
+        int r0 = 0;
+        for (; r0 + RB <= n; r0 += RB) {
+#pragma unroll
+            for (int kk = 0; kk < CPL; ++kk) {
+                if (l + kWave * kk < n)
+                    stream_batch<RB, FOLDX, false>(rp, rq, 4u * (uint32_t)(l + kWave * kk), rowb, n, r0, c1, s2, s3,
+                                                   s23, vmax, cs[kk]);
+                __builtin_amdgcn_sched_barrier(0);  // one column's batch at a time
+            }
+        }
+        if (r0 < n) {
+#pragma unroll
+            for (int kk = 0; kk < CPL; ++kk) {
+                if (l + kWave * kk < n)
+                    stream_batch<RB, FOLDX, true>(rp, rq, 4u * (uint32_t)(l + kWave * kk), rowb, n, r0, c1, s2, s3,
+                                                  s23, vmax, cs[kk]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    }
 #pragma unroll
     for (int kk = 0; kk < CPL; ++kk) {
         const int c = l + kWave * kk;
         const bool on = c < n;
-        int xr = 0;
-        float m1 = -INFINITY, m2 = -INFINITY, vx = 0.0f;
-        int r1 = -1;
+        const ColStream& z = cs[kk];
+        const int xr = (int)(z.rows & 0xffu);
+        const float m1 = z.m1, m2 = z.m2;
+        const int r1 = z.r1;
         if (on) {
-            Attract at;
-            xr = at.xr = Xk[c];
-            at.lr = gl(d.PL)[(size_t)k * n + c];
-            at.gr = gl(d.PG)[(size_t)gs * n + c];
-            // ox = -(s2 if P^L row differs) - (s3 if P^G row differs); ol = s2 (+ s3)
-            const bool nl = at.xr != at.lr, ng = at.xr != at.gr;
-            const DW o = nl && ng ? s23 : nl ? s2 : ng ? s3 : DW{0.0f, 0.0f};
-            at.ox = dw_neg(o);
-            at.ol = at.lr == at.gr ? s23 : s2;
-            const float sc = Sp[c];
-            const float sum = stream_column<NP >= 128>(rp, rq, c, n, sc, c1, s3, vmax, at, m1, r1, m2, vx);
+            const float sum = __fadd_rn(z.sum.hi, z.sum.lo);
             Sq[c] = (d.norm && sum > 0.0f) ? __fdiv_rn(1.0f, sum) : 1.0f;
         }
         // SecondTarget cache of the non-Z keys: exact (value, row, count 1)
@@ -510,7 +552,7 @@ __device__ __forceinline__ int velocity_and_target(const InstDesc& d, int k, uin
         st.cal[kk] = on;
         st.zal[kk] = on;
         st.zr[kk] = on ? xr : -1;
-        st.zk[kk] = on ? 1.0f + vx : -INFINITY;
+        st.zk[kk] = on ? 1.0f + z.vx : -INFINITY;
     }
 
     // ---- B. SecondTarget
@@ -619,8 +661,17 @@ __device__ __forceinline__ void fused_step_block(const InstDesc& d, int first)
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
+// Waves per SIMD the register allocation is held to (amdgpu_waves_per_eu).
+// Without it the compiler set 16 accumulation registers aside for the MFMA
+// results of the symmetric kernels on top of their VGPRs, which cost the
+// npad-96 kernels a wave per SIMD; with it those results stay in VGPRs.  The
+// general (asymmetric) kernels keep their 64 accumulation registers.
+template <int NP, bool SYM, bool ZD>
+constexpr int fused_min_waves() { return !SYM ? 1 : NP <= 96 ? 5 : NP == 128 ? 4 : 3; }
+
 template <int NP, bool SYM, bool ZD, bool TABLE, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(fused_min_waves<NP, SYM, ZD>())))
+void k_fused_step(InstDesc one, const InstDesc* __restrict__ descs,
                                                          const int2* __restrict__ blkmap)
 {
     if constexpr (TABLE) {
@@ -909,8 +960,18 @@ __device__ __forceinline__ void fused_wide_block(const InstDesc& d, int first)
     write_particle(d, k, cur, pw, goal, ba, bb);
 }
 
+// Waves per SIMD the register allocation of the byte-split kernels is held to
+// (as for k_fused_step).
+template <int NP, bool ZD, int SPLIT, int WPB>
+constexpr int wide_min_waves()
+{
+    return SPLIT == 3 ? (NP <= 32 ? 5 : NP == 64 ? 4 : NP == 96 ? 3 : 2)
+                      : (NP <= 64 ? 5 : NP == 96 ? 4 : NP == 128 ? (WPB == 8 ? 4 : 3) : 2);
+}
+
 template <int NP, bool ZD, int SPLIT, bool TABLE, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(wide_min_waves<NP, ZD, SPLIT, WPB>())))
+void k_fused_wide(InstDesc one, const InstDesc* __restrict__ descs,
                                                          const int2* __restrict__ blkmap)
 {
     if constexpr (TABLE) {

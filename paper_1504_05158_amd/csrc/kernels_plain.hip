@@ -39,13 +39,13 @@ __global__ void k_init_vel(InstDesc d)
     if (idx >= (long long)d.P * n) return;
     const int k = (int)(idx / n), c = (int)(idx % n);
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
-    float* V = d.V[0] + (size_t)k * n * vld(n);
+    float* V = d.V[0] + (size_t)k * n * n;
     DW sum{0.0f, 0.0f};
     for (int r = 0; r < n; ++r) {
         const float u = unit_float(stream_word(d.seed, 256u + (uint32_t)(r * n + c), 0, s, g));
         float t = __fmul_rn(d.vmax, __fsub_rn(__fmul_rn(2.0f, u), 1.0f));
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
-        V[(size_t)r * vld(n) + c] = t;
+        V[(size_t)r * n + c] = t;
         sum = dw_add_f(sum, fabsf(t));
     }
     const float tot = __fadd_rn(sum.hi, sum.lo);
@@ -78,13 +78,13 @@ __global__ void k_velocity(InstDesc d)
     const int x = d.X[cur][(size_t)k * n + c];
     const int pl = d.PL[(size_t)k * n + c];
     const int pg = d.PG[(size_t)gl * n + c];
-    const float* Vc = d.V[cur] + (size_t)k * n * vld(n);
+    const float* Vc = d.V[cur] + (size_t)k * n * n;
     const float sc = d.Vinv[cur][(size_t)k * n + c];
-    float* Vn = d.V[cur ^ 1] + (size_t)k * n * vld(n);
+    float* Vn = d.V[cur ^ 1] + (size_t)k * n * n;
     DW sum{0.0f, 0.0f};
     for (int r = 0; r < n; ++r) {
         const int a = (r == pl) - (r == x), b = (r == pg) - (r == x);
-        const float v = __fmul_rn(Vc[(size_t)r * vld(n) + c], sc);
+        const float v = __fmul_rn(Vc[(size_t)r * n + c], sc);
         float t;
         if (a | b) {
             const DW o = (a && b) ? s23 : a ? s2 : s3;
@@ -94,7 +94,7 @@ __global__ void k_velocity(InstDesc d)
         }
         t = fminf(fmaxf(t, -d.vmax), d.vmax);
         sum = dw_add_f(sum, fabsf(t));
-        Vn[(size_t)r * vld(n) + c] = t;
+        Vn[(size_t)r * n + c] = t;
     }
     const float tot = __fadd_rn(sum.hi, sum.lo);
     d.Vinv[cur ^ 1][(size_t)k * n + c] = (d.norm && tot > 0.0f) ? __fdiv_rn(1.0f, tot) : 1.0f;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void second_target_particle(const InstDesc& d, int k,
     const int n = d.n;
     const int cur = tprev & 1;
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
-    const float* V = d.V[cur] + (size_t)k * n * vld(n);
+    const float* V = d.V[cur] + (size_t)k * n * n;
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     StState<CPL> st;
     st_init_scan<CPL>(n, V, Vs, d.X[cur] + (size_t)k * n, st);
@@ -141,7 +141,7 @@ __device__ __forceinline__ void pick_column_particle(const InstDesc& d, int k, i
     const int cur = tprev & 1;
     const uint32_t tau = (uint32_t)tprev + 1u;
     const uint32_t g = (uint32_t)(k / d.S + d.swarm_base), s = (uint32_t)(k % d.S);
-    const float* V = d.V[cur] + (size_t)k * n * vld(n);
+    const float* V = d.V[cur] + (size_t)k * n * n;
     const float* Vs = d.Vinv[cur] + (size_t)k * n;
     const uint8_t* z = d.X[cur] + (size_t)k * n;
     for (int j = l; j < n - 1; j += kWave) w[j] = stream_word(d.seed, 4u + (uint32_t)(n + j), tau, s, g);
@@ -174,7 +174,7 @@ __device__ __forceinline__ void pick_column_particle(const InstDesc& d, int k, i
             const int r = l + kWave * j;
             key[j] = -INFINITY;
             if ((rowbits >> j) & 1u) {
-                const float x = __fmul_rn(V[(size_t)r * vld(n) + c], sc);
+                const float x = __fmul_rn(V[(size_t)r * n + c], sc);
                 key[j] = r == zc ? 1.0f + x : x;
             }
             best = fmaxf(best, key[j]);

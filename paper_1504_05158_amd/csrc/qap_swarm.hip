@@ -381,7 +381,7 @@ int setup_instance(qap_swarm* h, Instance& I, const qap_instance* in, const qap_
             *hi[m] = H;
         }
     }
-    const size_t nv = (size_t)n * qap::vld(n);  // padded rows
+    const size_t nv = (size_t)n * n;
     TRY(dalloc(I, &d.V[0], P * nv));
     TRY(dalloc(I, &d.V[1], P * nv));
     TRY(dalloc(I, &d.Vinv[0], P * n));
@@ -436,7 +436,7 @@ int init_state(qap_swarm* h, Instance& I)
 void make_groups(Instance& I, int groups)
 {
     const InstDesc& d = I.d;
-    const size_t n = (size_t)I.n, nv = n * qap::vld(I.n);  // padded V rows
+    const size_t n = (size_t)I.n, nv = n * n;
     I.groups = groups;
     I.gdesc.clear();
     for (int j = 0, g0 = 0; j < I.groups; ++j) {
@@ -1208,8 +1208,7 @@ int impl_get_state(qap_swarm* h, int32_t instance, qap_state* st)
     if (e == hipSuccess && st->V) {
         // V = fl(U * scale) per column, the value every kernel reads
         std::vector<float> sc(P * n);
-        e = hipMemcpy2D(st->V, n * sizeof(float), d.V[cur], (size_t)qap::vld((int)n) * sizeof(float), n * sizeof(float),
-                        P * n, hipMemcpyDeviceToHost);
+        e = hipMemcpy(st->V, d.V[cur], P * n * n * sizeof(float), hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(sc.data(), d.Vinv[cur], P * n * sizeof(float), hipMemcpyDeviceToHost);
         if (e == hipSuccess)
             for (size_t k = 0; k < P; ++k)
@@ -1270,8 +1269,7 @@ int impl_set_state(qap_swarm* h, int32_t instance, const qap_state* st)
         return hipMemcpy(dst, buf.data(), rows * n, hipMemcpyHostToDevice);
     };
     if (e == hipSuccess)
-        e = hipMemcpy2D(d.V[cur], (size_t)qap::vld((int)n) * sizeof(float), st->V, n * sizeof(float), n * sizeof(float),
-                        P * n, hipMemcpyHostToDevice);
+        e = hipMemcpy(d.V[cur], st->V, P * n * n * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         const std::vector<float> ones(P * n, 1.0f);
         e = hipMemcpy(d.Vinv[cur], ones.data(), P * n * sizeof(float), hipMemcpyHostToDevice);

@@ -1,6 +1,6 @@
 // S_x = SecondTarget (Alg. 1 of the paper) for one particle on one wave64.
 //
-// Input: the particle's V(t) (global, [n][vld(n)] unnormalised U with the
+// Input: the particle's V(t) (global, [n][n] unnormalised U with the
 // per-column scale Vs, V = fl(U * Vs); row = location, column = facility) and
 // its solution z = X(t).  Keys are W = X + V in binary32: a cell
 // of Z has key 1 + v, every other cell v.  Selection i = 0 .. n-1 takes the
@@ -51,7 +51,7 @@ __device__ __forceinline__ void st_rescan(int n, PV __restrict__ V, PV __restric
     for (int j = 0; j < CPL; ++j) {
         const int r = l + kWave * j;
         ok[j] = (r < n) && ((rowbits >> j) & 1u) && (r != zr);
-        v[j] = ok[j] ? __fmul_rn(V[(size_t)r * vld(n) + c], sc) : -INFINITY;
+        v[j] = ok[j] ? __fmul_rn(V[(size_t)r * n + c], sc) : -INFINITY;
         best = fmaxf(best, v[j]);
     }
     const float m = wave_max(best);
@@ -80,7 +80,7 @@ __device__ __forceinline__ int st_kth_tied_row(int n, PV __restrict__ V, PV __re
         bool ok = (r < n) && ((rowbits >> j) & 1u) && (withZ || r != zr);
         float key = -INFINITY;
         if (ok) {
-            const float v = __fmul_rn(V[(size_t)r * vld(n) + c], sc);
+            const float v = __fmul_rn(V[(size_t)r * n + c], sc);
             key = (r == zr) ? 1.0f + v : v;
         }
         const uint64_t b = ballot64(ok && key == m);
@@ -126,7 +126,7 @@ __device__ __forceinline__ void st_init_scan(int n, PV __restrict__ V, PV __rest
         for (int k = 0; k < CPL; ++k) {
             const int c = l + kWave * k;
             if (c < n) {
-                const float v = __fmul_rn(V[(size_t)r * vld(n) + c], sc[k]);
+                const float v = __fmul_rn(V[(size_t)r * n + c], sc[k]);
                 if (r == s.zr[k]) {
                     s.zk[k] = 1.0f + v;
                 } else if (v > s.nzv[k]) {
