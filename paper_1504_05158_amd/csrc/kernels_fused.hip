@@ -3,13 +3,14 @@
 // gfx950 int8 MFMA (v_mfma_i32_32x32x32_i8, int32 accumulation).
 //
 // Per particle (wave):
-//  A. stream V(t) once, lane = column (facility), 64 columns per pass (each
-//     load a 256-byte row segment): the velocity update of eq. (velocity) with
-//     the S_v clamp, the column norm (stored as a column scale applied on the
-//     next read), the store of V(t+1) into the other buffer, and the
-//     SecondTarget column caches (max key, Z-cell key).  The at most three
-//     cells per column touched by the attraction terms (rows of X, P^L, P^G)
-//     are corrected after the pass.
+//  A. stream V(t) once, lane = column (facility), the lane's columns l, l + 64,
+//     ... taken through each batch of rows in turn (each load a 256-byte row
+//     segment): the velocity update of eq. (velocity) with the S_v clamp, the
+//     column norm (stored as a column scale applied on the next read), the
+//     store of V(t+1) into the other buffer, and the SecondTarget column caches
+//     (max key, Z-cell key).  The at most three cells per column touched by
+//     the attraction terms (rows of X, P^L, P^G) are corrected right after
+//     the batch that holds them.
 //  B. SecondTarget (Alg. 1) on X(t) + V(t), rescans reading V(t) from L2.
 //  C. A = F . Dp^T and A^T = Dp . F^T (Dp[y][k] = D[p_y][p_k]) tile by tile
 //     on MFMA; goal = trace(A); for every pair x < y
