@@ -76,6 +76,12 @@ CASES = [
     dict(n=40, kind="sym", norm=True, depth=2, ls=3),
     dict(n=33, kind="gen", norm=True, depth=2, ls=4),
     dict(n=128, kind="sym", norm=True, depth=2, ls=1000),   # to a pair-exchange local optimum
+    # column slots of the velocity pass: one lane in the second slot, no tail
+    # batch, a ragged second slot at npad 128, one lane in the third slot
+    dict(n=65, kind="sym", norm=True, depth=2, ls=True),
+    dict(n=80, kind="gen", norm=True, depth=2, ls=True),
+    dict(n=97, kind="sym", norm=True, depth=2, ls=True),
+    dict(n=129, kind="sym", norm=False, depth=2, ls=True),
 ]
 
 
