@@ -280,8 +280,10 @@ __device__ void gemm_to_scratch(int n, const int* __restrict__ Fm, const int* __
                     Ds[i][kk] = (y < n && kx < n) ? Dm[(size_t)pl[y] * n + pl[kx]] : 0;
                 }
                 __syncthreads();
+                // the chunk's columns past n are zero: stop at n
+                const int kend = min(kKc, n - k0);
 #pragma unroll 4
-                for (int kk = 0; kk < kKc; ++kk) {
+                for (int kk = 0; kk < kend; ++kk) {
                     int fa[4], db[4];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) { fa[u] = Fs[ti * 4 + u][kk]; db[u] = Ds[tj * 4 + u][kk]; }
@@ -312,6 +314,7 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
     __shared__ int Ds[kTile][kKc + 1];
     __shared__ uint8_t pl[kMaxN];
     __shared__ long long diag[kMaxN];
+    __shared__ int fdiag[kMaxN], ddiag[kMaxN];  // f_aa and Dp_aa = D[p_a][p_a]
     __shared__ long long red_d[4];
     __shared__ int red_a[4], red_b[4];
     __shared__ long long red_goal[4];
@@ -351,8 +354,9 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
                             Ds[i][kk] = (y < n && kx < n) ? d.D32[(size_t)pl[kx] * n + pl[y]] : 0;
                         }
                         __syncthreads();
+                        const int kend = min(kKc, n - k0);
 #pragma unroll 4
-                        for (int kk = 0; kk < kKc; ++kk) {
+                        for (int kk = 0; kk < kend; ++kk) {
                             int fa[4], db[4];
 #pragma unroll
                             for (int u = 0; u < 4; ++u) { fa[u] = Fs[ti * 4 + u][kk]; db[u] = Ds[tj * 4 + u][kk]; }
@@ -379,6 +383,8 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
             const long long da = (long long)A[(size_t)a * n + a];
             diag[a] = GEN ? da + (long long)B[(size_t)a * n + a] : 2 * da;
             gpart += da;
+            fdiag[a] = d.F32[(size_t)a * n + a];
+            ddiag[a] = d.D32[(size_t)pl[a] * n + pl[a]];
         }
         gpart = wave_sum_i64(gpart);
         if (l == 0) red_goal[w] = gpart;
@@ -389,13 +395,13 @@ __global__ __launch_bounds__(256) void k_goal_delta_i32(InstDesc d, const uint8_
         ba = 0x7fffffff;
         bb = 0x7fffffff;
         if (mode != 2) {
-            for (int q = tid; q < n * n; q += 256) {
-                const int a = q / n, b = q % n;
-                if (a >= b) continue;
+            // wave w takes the rows a = w, w + 4, ..., its lanes the b > a
+            for (int a = w; a < n - 1; a += 4)
+            for (int b = a + 1 + l; b < n; b += 64) {
                 const int pa = pl[a], pb = pl[b];
-                const long long faa = d.F32[(size_t)a * n + a], fbb = d.F32[(size_t)b * n + b];
+                const long long faa = fdiag[a], fbb = fdiag[b];
                 const long long fab = d.F32[(size_t)a * n + b], fba = d.F32[(size_t)b * n + a];
-                const long long Daa = d.D32[(size_t)pa * n + pa], Dbb = d.D32[(size_t)pb * n + pb];
+                const long long Daa = ddiag[a], Dbb = ddiag[b];
                 const long long Dab = d.D32[(size_t)pa * n + pb], Dba = d.D32[(size_t)pb * n + pa];
                 long long s = (long long)A[(size_t)a * n + b] + (long long)A[(size_t)b * n + a];
                 if (GEN) s += (long long)B[(size_t)a * n + b] + (long long)B[(size_t)b * n + a];
